@@ -1,0 +1,771 @@
+/*
+ * oracle.c -- plain CPU oracle of the ternary flip-graph random walk.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Deliberately simple: int8 arrays,
+ * linear scans, no bit tricks, no blocking or reordering of the steps.
+ */
+#include "oracle.h"
+
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from the published definition (Salmon et al., "Parallel    */
+/* random numbers: as easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64  */
+/* multiplications with a Weyl-sequence key schedule.                        */
+/* ------------------------------------------------------------------------ */
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The walk's random words.  Reading (the paper only says each scheme has its
+ * own generator, Sec. 3.4.2): one Philox block per (iteration t, attempt a,
+ * domain d), key = the 64-bit walk seed, counter = (t lo, t hi, a, d).
+ * Domains: 0 flip attempts, 1 per-iteration gates, 2 expand attempts. */
+static void draw(uint64_t seed, int64_t t, uint32_t a, uint32_t dom, uint32_t w[4])
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)(uint64_t)t, (uint32_t)((uint64_t)t >> 32), a, dom };
+    or_philox(ctr, key, w);
+}
+
+/* uniform integer in [0, n): floor(word * n / 2^32) */
+static int uniform_below(uint32_t word, int n)
+{
+    return (int)(((uint64_t)word * (uint64_t)(uint32_t)n) >> 32);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Schemes                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* lengths of the flattened factors: U is m x n, V is n x p, W is p x m (Sec. 3.1) */
+int or_len(const or_scheme *s, int X)
+{
+    if (X == OR_U) return s->m * s->n;
+    if (X == OR_V) return s->n * s->p;
+    return s->p * s->m;
+}
+
+static int vec_zero(const int8_t *a, int len)
+{
+    for (int e = 0; e < len; ++e)
+        if (a[e] != 0) return 0;
+    return 1;
+}
+
+static int vec_eq(const int8_t *a, const int8_t *b, int len)
+{
+    for (int e = 0; e < len; ++e)
+        if (a[e] != b[e]) return 0;
+    return 1;
+}
+
+static int vec_neg_eq(const int8_t *a, const int8_t *b, int len)
+{
+    for (int e = 0; e < len; ++e)
+        if (a[e] != -b[e]) return 0;
+    return 1;
+}
+
+/* out = a + sign*b.  Ternary: valid iff every entry stays in {-1,0,1}
+ * (the "valid" flag of the one-bit representation, Sec. 3.5.1-3.5.2).
+ * Z2: addition modulo 2, always valid, sign ignored. */
+int or_ternary_add(const int8_t *a, const int8_t *b, int sign, int len, int z2, int8_t *out)
+{
+    int ok = 1;
+    for (int e = 0; e < len; ++e) {
+        int x;
+        if (z2) {
+            x = (a[e] + b[e]) % 2;
+        } else {
+            x = a[e] + sign * b[e];
+            if (x < -1 || x > 1) ok = 0;
+        }
+        out[e] = (int8_t)x;
+    }
+    return ok;
+}
+
+static void copy_term(or_scheme *s, int dst, int src)
+{
+    for (int X = 0; X < 3; ++X)
+        memcpy(s->f[X][dst], s->f[X][src], OR_MAXL);
+}
+
+/* Standard rank-mnp scheme: one term a_ij (x) b_jk (x) c_ik for each (i,j,k),
+ * in lexicographic (i,j,k) order. */
+void or_standard(or_scheme *s, int m, int n, int p, int z2)
+{
+    memset(s, 0, sizeof(*s));
+    s->m = m; s->n = n; s->p = p; s->z2 = z2;
+    int l = 0;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < p; ++k) {
+                s->f[OR_U][l][i * n + j] = 1;
+                s->f[OR_V][l][j * p + k] = 1;
+                s->f[OR_W][l][k * m + i] = 1;
+                ++l;
+            }
+    s->r = l;
+}
+
+/* Brent equations (Eq. 1) in the C^T form of Sec. 3.1: for every
+ * a_{a1 a2}, b_{b1 b2} and c^T entry (c1,c2) = w[c1*m + c2],
+ *     sum_l u_l[a1*n+a2] v_l[b1*p+b2] w_l[c1*m+c2] = [a2==b1][b2==c1][c2==a1].
+ * Returns the number of violated equations (mod 2 in Z2). */
+long or_brent_violations(const or_scheme *s)
+{
+    int m = s->m, n = s->n, p = s->p;
+    long bad = 0;
+    for (int a1 = 0; a1 < m; ++a1)
+        for (int a2 = 0; a2 < n; ++a2)
+            for (int b1 = 0; b1 < n; ++b1)
+                for (int b2 = 0; b2 < p; ++b2)
+                    for (int c1 = 0; c1 < p; ++c1)
+                        for (int c2 = 0; c2 < m; ++c2) {
+                            long sum = 0;
+                            for (int l = 0; l < s->r; ++l)
+                                sum += (long)s->f[OR_U][l][a1 * n + a2] *
+                                       (long)s->f[OR_V][l][b1 * p + b2] *
+                                       (long)s->f[OR_W][l][c1 * m + c2];
+                            long want = (a2 == b1 && b2 == c1 && c2 == a1) ? 1 : 0;
+                            if (s->z2) {
+                                if (((sum % 2) + 2) % 2 != want) ++bad;
+                            } else if (sum != want) {
+                                ++bad;
+                            }
+                        }
+    return bad;
+}
+
+/* Naive additive complexity (Sec. 4.5): non-zero coefficients - 2r - m*p. */
+long or_naive_additions(const or_scheme *s)
+{
+    long nnz = 0;
+    for (int X = 0; X < 3; ++X)
+        for (int l = 0; l < s->r; ++l)
+            for (int e = 0; e < or_len(s, X); ++e)
+                if (s->f[X][l][e] != 0) ++nnz;
+    return nnz - 2L * s->r - (long)s->m * s->p;
+}
+
+/* Sign-symmetry normalisation (Sec. 3.6).  Reading, fixed by the worked
+ * (2,2,2:7) example there: per term (row), the first non-zero entry (lowest
+ * flattened index) of u and then of v is made positive; w absorbs each sign
+ * change (alpha*beta*gamma = 1).  w itself is never normalised.  No-op in Z2. */
+void or_normalise_term(or_scheme *s, int l)
+{
+    if (s->z2) return;
+    for (int X = OR_U; X <= OR_V; ++X) {
+        int len = or_len(s, X);
+        for (int e = 0; e < len; ++e) {
+            if (s->f[X][l][e] == 0) continue;
+            if (s->f[X][l][e] < 0) {
+                for (int q = 0; q < len; ++q) s->f[X][l][q] = (int8_t)-s->f[X][l][q];
+                int lw = or_len(s, OR_W);
+                for (int q = 0; q < lw; ++q) s->f[OR_W][l][q] = (int8_t)-s->f[OR_W][l][q];
+            }
+            break;
+        }
+    }
+}
+
+int or_is_normalised(const or_scheme *s)
+{
+    if (s->z2) return 1;
+    for (int l = 0; l < s->r; ++l)
+        for (int X = OR_U; X <= OR_V; ++X)
+            for (int e = 0; e < or_len(s, X); ++e)
+                if (s->f[X][l][e] != 0) {
+                    if (s->f[X][l][e] < 0) return 0;
+                    break;
+                }
+    return 1;
+}
+
+/* swap-remove: the last term moves into slot h.  Tracked indices follow the
+ * move; a tracked index equal to h is dropped (-1). */
+static void swap_remove(or_scheme *s, int h, int *track, int n_track)
+{
+    int last = s->r - 1;
+    for (int q = 0; q < n_track; ++q)
+        if (track[q] == h) track[q] = -1;
+    if (h != last) {
+        copy_term(s, h, last);
+        for (int q = 0; q < n_track; ++q)
+            if (track[q] == last) track[q] = h;
+    }
+    memset(s->f[OR_U][last], 0, OR_MAXL);
+    memset(s->f[OR_V][last], 0, OR_MAXL);
+    memset(s->f[OR_W][last], 0, OR_MAXL);
+    s->r -= 1;
+}
+
+static int term_has_zero_factor(const or_scheme *s, int l)
+{
+    for (int X = 0; X < 3; ++X)
+        if (vec_zero(s->f[X][l], or_len(s, X))) return 1;
+    return 0;
+}
+
+/* Remove every term with a zero factor, highest index first (swap-remove). */
+int or_remove_zero_terms(or_scheme *s)
+{
+    int removed = 0;
+    for (int l = s->r - 1; l >= 0; --l)
+        if (term_has_zero_factor(s, l)) {
+            swap_remove(s, l, NULL, 0);
+            ++removed;
+        }
+    return removed;
+}
+
+/* the two factor kinds other than X, in U<V<W order, swapped when role = 1 */
+static void other_kinds(int X, int role, int *Y, int *Z)
+{
+    int a, b;
+    if (X == OR_U) { a = OR_V; b = OR_W; }
+    else if (X == OR_V) { a = OR_U; b = OR_W; }
+    else { a = OR_U; b = OR_V; }
+    if (role) { *Y = b; *Z = a; } else { *Y = a; *Z = b; }
+}
+
+/* Flip (Sec. 3.3.1) of the ordered pair (i,j) sharing factor X up to the sign
+ * sigma (x_j = sigma*x_i), with (Y,Z) the other two kinds:
+ *   x_i(x)y_i(x)z_i + x_j(x)y_j(x)z_j
+ *     -> x_i(x)(y_i + sigma*y_j)(x)z_i + x_j(x)y_j(x)(z_j - z_i).
+ * The paper writes sigma = +1 with (Y,Z) = (V,W); every permutation of the
+ * roles is allowed (Sec. 3.3.1) and, since w keeps its sign freedom after
+ * normalisation (Sec. 3.6), sigma = -1 occurs for X = W.
+ * Returns 1 if both new factors are ternary-valid (Sec. 3.5.2). */
+int or_flip_valid(const or_scheme *s, int i, int j, int X, int sigma, int role)
+{
+    int Y, Z;
+    int8_t tmp[OR_MAXL] = { 0 };
+    other_kinds(X, role, &Y, &Z);
+    if (!or_ternary_add(s->f[Y][i], s->f[Y][j], sigma, or_len(s, Y), s->z2, tmp)) return 0;
+    if (!or_ternary_add(s->f[Z][j], s->f[Z][i], -1, or_len(s, Z), s->z2, tmp)) return 0;
+    return 1;
+}
+
+int or_flip(or_scheme *s, int i, int j, int X, int sigma, int role)
+{
+    int Y, Z;
+    int8_t ny[OR_MAXL] = { 0 }, nz[OR_MAXL] = { 0 };
+    other_kinds(X, role, &Y, &Z);
+    if (!or_ternary_add(s->f[Y][i], s->f[Y][j], sigma, or_len(s, Y), s->z2, ny)) return 0;
+    if (!or_ternary_add(s->f[Z][j], s->f[Z][i], -1, or_len(s, Z), s->z2, nz)) return 0;
+    memcpy(s->f[Y][i], ny, OR_MAXL);
+    memcpy(s->f[Z][j], nz, OR_MAXL);
+    or_normalise_term(s, i);
+    or_normalise_term(s, j);
+    return 1;
+}
+
+/* sign relating factor X of terms i and j: +1 if equal, -1 if negated
+ * (only for W, Sec. 3.6, and never in Z2), 0 otherwise */
+static int shared_sign(const or_scheme *s, int i, int j, int X)
+{
+    int len = or_len(s, X);
+    if (vec_eq(s->f[X][j], s->f[X][i], len)) return 1;
+    if (!s->z2 && X == OR_W && vec_neg_eq(s->f[X][j], s->f[X][i], len)) return -1;
+    return 0;
+}
+
+/* role permutations (X,Y,Z) of (U,V,W) in lexicographic order */
+static const int PERMS[6][3] = {
+    { OR_U, OR_V, OR_W }, { OR_U, OR_W, OR_V }, { OR_V, OR_U, OR_W },
+    { OR_V, OR_W, OR_U }, { OR_W, OR_U, OR_V }, { OR_W, OR_V, OR_U },
+};
+
+/* Plus (Sec. 3.3.1), roles (X,Y,Z) = PERMS[perm]:
+ *   x_i(x)y_i(x)z_i + x_j(x)y_j(x)z_j
+ *     -> x_i(x)(y_i+y_j)(x)z_i + x_i(x)y_j(x)(z_j-z_i) + (x_j-x_i)(x)y_j(x)z_j,
+ * allowed when x_i!=x_j, y_i!=y_j, z_i!=z_j.  Reading: also every new factor
+ * must be ternary-valid and y_i+y_j non-zero.  The third term is appended. */
+int or_plus(or_scheme *s, int i, int j, int perm)
+{
+    int X = PERMS[perm][0], Y = PERMS[perm][1], Z = PERMS[perm][2];
+    int lx = or_len(s, X), ly = or_len(s, Y), lz = or_len(s, Z);
+    int8_t a[OR_MAXL] = { 0 }, b[OR_MAXL] = { 0 }, c[OR_MAXL] = { 0 };
+    if (s->r >= OR_MAXT) return 0;
+    if (vec_eq(s->f[X][i], s->f[X][j], lx) || vec_eq(s->f[Y][i], s->f[Y][j], ly) ||
+        vec_eq(s->f[Z][i], s->f[Z][j], lz))
+        return 0;
+    if (!or_ternary_add(s->f[Y][i], s->f[Y][j], 1, ly, s->z2, a) || vec_zero(a, ly)) return 0;
+    if (!or_ternary_add(s->f[Z][j], s->f[Z][i], -1, lz, s->z2, b)) return 0;
+    if (!or_ternary_add(s->f[X][j], s->f[X][i], -1, lx, s->z2, c)) return 0;
+    int nw = s->r;
+    memset(s->f[OR_U][nw], 0, OR_MAXL);
+    memset(s->f[OR_V][nw], 0, OR_MAXL);
+    memset(s->f[OR_W][nw], 0, OR_MAXL);
+    memcpy(s->f[X][nw], c, OR_MAXL);
+    memcpy(s->f[Y][nw], s->f[Y][j], OR_MAXL);
+    memcpy(s->f[Z][nw], s->f[Z][j], OR_MAXL);
+    memcpy(s->f[X][j], s->f[X][i], OR_MAXL);
+    memcpy(s->f[Z][j], b, OR_MAXL);
+    memcpy(s->f[Y][i], a, OR_MAXL);
+    s->r += 1;
+    or_normalise_term(s, i);
+    or_normalise_term(s, j);
+    or_normalise_term(s, nw);
+    return 1;
+}
+
+/* Split (Sec. 3.3.1), X = PERMS[perm][0]:
+ *   x_i(x)y_i(x)z_i + x_j(x)y_j(x)z_j
+ *     -> x_j(x)y_i(x)z_i + x_j(x)y_j(x)z_j + (x_i-x_j)(x)y_i(x)z_i,
+ * allowed when x_i != x_j; reading: x_i-x_j must be ternary-valid. */
+int or_split(or_scheme *s, int i, int j, int perm)
+{
+    int X = PERMS[perm][0];
+    int lx = or_len(s, X);
+    int8_t c[OR_MAXL] = { 0 };
+    if (s->r >= OR_MAXT) return 0;
+    if (vec_eq(s->f[X][i], s->f[X][j], lx)) return 0;
+    if (!or_ternary_add(s->f[X][i], s->f[X][j], -1, lx, s->z2, c)) return 0;
+    int nw = s->r;
+    copy_term(s, nw, i);
+    memcpy(s->f[X][nw], c, OR_MAXL);
+    memcpy(s->f[X][i], s->f[X][j], OR_MAXL);
+    s->r += 1;
+    or_normalise_term(s, i);
+    or_normalise_term(s, j);
+    or_normalise_term(s, nw);
+    return 1;
+}
+
+/* Reduction (Sec. 3.3.1): terms t and k sharing two factors merge into one.
+ * The shared pair is tried in the order (U,V)->merge W, (U,W)->merge V,
+ * (V,W)->merge U; w may be shared up to sign (Sec. 3.6), u and v only
+ * exactly.  On success returns the merged kind and writes the merged factor
+ * into out; returns -1 if no ternary-valid merge exists for the pair. */
+static int merge_candidate(const or_scheme *s, int t, int k, int8_t *out)
+{
+    int lu = or_len(s, OR_U), lv = or_len(s, OR_V), lw = or_len(s, OR_W);
+    int eq_u = vec_eq(s->f[OR_U][k], s->f[OR_U][t], lu);
+    int eq_v = vec_eq(s->f[OR_V][k], s->f[OR_V][t], lv);
+    int sg_w = shared_sign(s, t, k, OR_W);
+    if (eq_u && eq_v) {
+        /* u(x)v(x)w_t + u(x)v(x)w_k = u(x)v(x)(w_t + w_k) */
+        if (or_ternary_add(s->f[OR_W][t], s->f[OR_W][k], 1, lw, s->z2, out)) return OR_W;
+    }
+    if (eq_u && sg_w != 0) {
+        /* u(x)v_t(x)w + u(x)v_k(x)(sg*w) = u(x)(v_t + sg*v_k)(x)w */
+        if (or_ternary_add(s->f[OR_V][t], s->f[OR_V][k], sg_w, lv, s->z2, out)) return OR_V;
+    }
+    if (eq_v && sg_w != 0) {
+        if (or_ternary_add(s->f[OR_U][t], s->f[OR_U][k], sg_w, lu, s->z2, out)) return OR_U;
+    }
+    return -1;
+}
+
+/* Reduce the tracked (modified) terms against every other term, cascading:
+ * for each tracked term in order, scan k = 0..r-1 ascending for the first
+ * pair with a valid merge; the merged term goes to slot min(t,k), slot
+ * max(t,k) is swap-removed, and the scan restarts on the merged term.  A
+ * merged factor of zero removes both terms (higher slot first).  Returns the
+ * number of merges. */
+static int reduce_tracked(or_scheme *s, int *track, int n_track)
+{
+    int merges = 0;
+    int8_t merged[OR_MAXL] = { 0 };
+    for (int q = 0; q < n_track; ++q) {
+        for (;;) {
+            int t = track[q];
+            if (t < 0) break;
+            int k, kind = -1;
+            for (k = 0; k < s->r; ++k) {
+                if (k == t) continue;
+                kind = merge_candidate(s, t, k, merged);
+                if (kind >= 0) break;
+            }
+            if (kind < 0) break;
+            ++merges;
+            int lo = t < k ? t : k, hi = t < k ? k : t;
+            for (int o = 0; o < n_track; ++o)
+                if (o != q && track[o] == k) track[o] = -1;
+            if (vec_zero(merged, or_len(s, kind))) {
+                /* both terms cancel; lo < hi <= r-1, so removing hi first
+                 * never moves lo */
+                track[q] = -1;
+                swap_remove(s, hi, track, n_track);
+                swap_remove(s, lo, track, n_track);
+                break;
+            }
+            if (lo != t) copy_term(s, lo, t);
+            memcpy(s->f[kind][lo], merged, OR_MAXL);
+            or_normalise_term(s, lo);
+            track[q] = lo;
+            swap_remove(s, hi, track, n_track);
+        }
+    }
+    return merges;
+}
+
+/* Full reduction pass used for imported schemes: remove zero terms, then
+ * treat every term as modified and reduce to a fixpoint. */
+int or_full_reduce(or_scheme *s)
+{
+    int total = 0;
+    or_remove_zero_terms(s);
+    for (int l = 0; l < s->r; ++l) or_normalise_term(s, l);
+    for (;;) {
+        int merged = 0;
+        for (int l = 0; l < s->r; ++l) {
+            int tr[1] = { l };
+            int got = reduce_tracked(s, tr, 1);
+            if (got) { merged += got; break; }
+        }
+        if (!merged) break;
+        total += merged;
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Meta operators (Sec. 3.3.2)                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Project (m,n,p) -> one dimension smaller: drop index `index` of axis
+ * (0 = m, 1 = n, 2 = p) from every factor it appears in, then remove the
+ * terms that became zero. */
+int or_project(const or_scheme *in, int axis, int index, or_scheme *out)
+{
+    int m = in->m, n = in->n, p = in->p;
+    int dims[3] = { m, n, p };
+    if (axis < 0 || axis > 2 || index < 0 || index >= dims[axis] || dims[axis] < 2) return -1;
+    int m2 = m - (axis == 0), n2 = n - (axis == 1), p2 = p - (axis == 2);
+    memset(out, 0, sizeof(*out));
+    out->m = m2; out->n = n2; out->p = p2; out->z2 = in->z2; out->r = in->r;
+    for (int l = 0; l < in->r; ++l) {
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) {
+                if ((axis == 0 && i == index) || (axis == 1 && j == index)) continue;
+                int i2 = i - (axis == 0 && i > index), j2 = j - (axis == 1 && j > index);
+                out->f[OR_U][l][i2 * n2 + j2] = in->f[OR_U][l][i * n + j];
+            }
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < p; ++k) {
+                if ((axis == 1 && j == index) || (axis == 2 && k == index)) continue;
+                int j2 = j - (axis == 1 && j > index), k2 = k - (axis == 2 && k > index);
+                out->f[OR_V][l][j2 * p2 + k2] = in->f[OR_V][l][j * p + k];
+            }
+        for (int k = 0; k < p; ++k)
+            for (int i = 0; i < m; ++i) {
+                if ((axis == 2 && k == index) || (axis == 0 && i == index)) continue;
+                int k2 = k - (axis == 2 && k > index), i2 = i - (axis == 0 && i > index);
+                out->f[OR_W][l][k2 * m2 + i2] = in->f[OR_W][l][k * m + i];
+            }
+    }
+    or_remove_zero_terms(out);
+    for (int l = 0; l < out->r; ++l) or_normalise_term(out, l);
+    return 0;
+}
+
+/* Extend (Sec. 3.3.2): (m,n,p:r) -> (m,n,p+1:r+mn) by appending the naive
+ * (m,n,1) scheme for the new index, terms in (i,j) order; likewise along m
+ * (+np terms, (j,k) order) and n (+mp terms, (i,k) order). */
+int or_extend(const or_scheme *in, int axis, or_scheme *out)
+{
+    int m = in->m, n = in->n, p = in->p;
+    if (axis < 0 || axis > 2) return -1;
+    int m2 = m + (axis == 0), n2 = n + (axis == 1), p2 = p + (axis == 2);
+    if (m2 * n2 > OR_MAXL || n2 * p2 > OR_MAXL || p2 * m2 > OR_MAXL) return -1;
+    int extra = axis == 0 ? n * p : axis == 1 ? m * p : m * n;
+    if (in->r + extra > OR_MAXT) return -1;
+    memset(out, 0, sizeof(*out));
+    out->m = m2; out->n = n2; out->p = p2; out->z2 = in->z2; out->r = in->r;
+    for (int l = 0; l < in->r; ++l) {
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) out->f[OR_U][l][i * n2 + j] = in->f[OR_U][l][i * n + j];
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < p; ++k) out->f[OR_V][l][j * p2 + k] = in->f[OR_V][l][j * p + k];
+        for (int k = 0; k < p; ++k)
+            for (int i = 0; i < m; ++i) out->f[OR_W][l][k * m2 + i] = in->f[OR_W][l][k * m + i];
+    }
+    int l = in->r;
+    if (axis == 2) {
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j, ++l) {
+                out->f[OR_U][l][i * n2 + j] = 1;
+                out->f[OR_V][l][j * p2 + p] = 1;
+                out->f[OR_W][l][p * m2 + i] = 1;
+            }
+    } else if (axis == 0) {
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < p; ++k, ++l) {
+                out->f[OR_U][l][m * n2 + j] = 1;
+                out->f[OR_V][l][j * p2 + k] = 1;
+                out->f[OR_W][l][k * m2 + m] = 1;
+            }
+    } else {
+        for (int i = 0; i < m; ++i)
+            for (int k = 0; k < p; ++k, ++l) {
+                out->f[OR_U][l][i * n2 + n] = 1;
+                out->f[OR_V][l][n * p2 + k] = 1;
+                out->f[OR_W][l][k * m2 + i] = 1;
+            }
+    }
+    out->r = l;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The walk: Algorithm 1 (RandomWalk kernel, Sec. 3.4.2)                     */
+/* ------------------------------------------------------------------------ */
+
+void or_walk_init(or_walk *w, const or_scheme *start)
+{
+    memset(w, 0, sizeof(*w));
+    w->start = *start;
+    for (int l = 0; l < w->start.r; ++l) or_normalise_term(&w->start, l);
+    w->cur = w->start;
+    w->best = w->start;
+    w->best_rank = w->start.r;
+}
+
+/* Is (j, sigma, role) a valid flip partner of (i, X)? */
+static int partner(const or_scheme *s, int i, int j, int X, int role, int *sigma)
+{
+    if (j == i) return 0;
+    int sg = shared_sign(s, i, j, X);
+    if (sg == 0) return 0;
+    if (!or_flip_valid(s, i, j, X, sg, role)) return 0;
+    *sigma = sg;
+    return 1;
+}
+
+/* try_flip of Algorithm 1.  Reading (the paper does not fix how a flip is
+ * sampled): attempt a = 0..flip_tries-1 draws block (t,a,0): term
+ * i = U(w0, r), factor X = U(w1, 3); its candidates are the valid
+ * (j, role) in order role 0 then 1, j ascending; a non-empty list yields
+ * candidate U(w2, |list|).  If every attempt is empty, all valid (i, X,
+ * role, j) in that nesting order are enumerated and entry U(w0, count) of
+ * block (t, flip_tries, 0) is taken.  Only when no valid flip exists at all
+ * does try_flip fail.  On success *pi and *pj hold the modified terms. */
+static int try_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *pj)
+{
+    or_scheme *s = &w->cur;
+    int r = s->r;
+    uint32_t rw[4];
+    if (r < 2) return 0;
+    for (int a = 0; a < prm->flip_tries; ++a) {
+        draw(prm->seed, t, (uint32_t)a, 0, rw);
+        w->c.attempts++;
+        int i = uniform_below(rw[0], r);
+        int X = uniform_below(rw[1], 3);
+        int cj[2 * OR_MAXT], cs[2 * OR_MAXT], cr[2 * OR_MAXT];
+        int nc = 0;
+        for (int role = 0; role < 2; ++role)
+            for (int j = 0; j < r; ++j) {
+                int sg;
+                if (partner(s, i, j, X, role, &sg)) {
+                    cj[nc] = j; cs[nc] = sg; cr[nc] = role; ++nc;
+                }
+            }
+        if (nc > 0) {
+            int c = uniform_below(rw[2], nc);
+            or_flip(s, i, cj[c], X, cs[c], cr[c]);
+            *pi = i; *pj = cj[c];
+            return 1;
+        }
+    }
+    /* exhaustive fallback */
+    w->c.fallbacks++;
+    long count = 0;
+    for (int i = 0; i < r; ++i)
+        for (int X = 0; X < 3; ++X)
+            for (int role = 0; role < 2; ++role)
+                for (int j = 0; j < r; ++j) {
+                    int sg;
+                    if (partner(s, i, j, X, role, &sg)) ++count;
+                }
+    if (count == 0) return 0;
+    draw(prm->seed, t, (uint32_t)prm->flip_tries, 0, rw);
+    long pick = uniform_below(rw[0], (int)count);
+    for (int i = 0; i < r; ++i)
+        for (int X = 0; X < 3; ++X)
+            for (int role = 0; role < 2; ++role)
+                for (int j = 0; j < r; ++j) {
+                    int sg;
+                    if (!partner(s, i, j, X, role, &sg)) continue;
+                    if (pick-- == 0) {
+                        or_flip(s, i, j, X, sg, role);
+                        *pi = i; *pj = j;
+                        return 1;
+                    }
+                }
+    return 0; /* unreachable */
+}
+
+/* expand of Algorithm 1 (plus or split, 50/50, Sec. 3.3.1).  Reading: up to
+ * eight attempts; attempt a draws block (t,a,2): i = U(w0, r),
+ * j = U(w1, r-1) shifted past i, roles PERMS[U(w2, 6)], and the top bit of
+ * w3 picks plus (0) or split (1).  Refused when the rank reached r_cap. */
+static int expand(or_walk *w, const or_params *prm, int64_t t)
+{
+    or_scheme *s = &w->cur;
+    int r = s->r;
+    uint32_t rw[4];
+    if (r >= prm->r_cap || r < 2 || r >= OR_MAXT) return 0;
+    for (int a = 0; a < 8; ++a) {
+        draw(prm->seed, t, (uint32_t)a, 2, rw);
+        int i = uniform_below(rw[0], r);
+        int j = uniform_below(rw[1], r - 1);
+        if (j >= i) ++j;
+        int perm = uniform_below(rw[2], 6);
+        int ok = (rw[3] >> 31) ? or_split(s, i, j, perm) : or_plus(s, i, j, perm);
+        if (ok) {
+            w->c.expands++;
+            return 1;
+        }
+    }
+    w->c.expand_fails++;
+    return 0;
+}
+
+static void restart_check(or_walk *w, const or_params *prm, int64_t t)
+{
+    if (prm->plateau > 0 && t - w->plateau_start >= prm->plateau) {
+        w->cur = prm->restart_from_best ? w->best : w->start;
+        w->plateau_start = t;
+        w->c.restarts++;
+    }
+}
+
+static void one_iteration(or_walk *w, const or_params *prm, int64_t t)
+{
+    or_scheme *s = &w->cur;
+    int i = -1, j = -1;
+    w->c.iters++;
+    if (!try_flip(w, prm, t, &i, &j)) {
+        /* Algorithm 1: no flip -> expand, continue */
+        w->c.dead_ends++;
+        expand(w, prm, t);
+        restart_check(w, prm, t);
+        return;
+    }
+    w->c.flips++;
+
+    /* a flip that makes a factor zero is a reduction edge: the zero term
+     * leaves the scheme at once (higher slot first, swap-remove) */
+    int track[2] = { i, j };
+    int zi = term_has_zero_factor(s, i), zj = term_has_zero_factor(s, j);
+    if (zi && zj) {
+        int hi = i > j ? i : j, lo = i > j ? j : i;
+        swap_remove(s, hi, track, 2);
+        swap_remove(s, lo, track, 2);
+        w->c.zero_removed += 2;
+    } else if (zi) {
+        swap_remove(s, i, track, 2);
+        w->c.zero_removed++;
+    } else if (zj) {
+        swap_remove(s, j, track, 2);
+        w->c.zero_removed++;
+    }
+
+    uint32_t g[4];
+    draw(prm->seed, t, 0, 1, g);
+    /* best update: strictly better always, equal rank with probability 0.01 */
+    if (s->r < w->best_rank) {
+        w->best = *s;
+        w->best_rank = s->r;
+        w->plateau_start = t;
+        if (w->n_rec < OR_MAXREC) {
+            w->rec_iter[w->n_rec] = t;
+            w->rec_rank[w->n_rec] = s->r;
+        }
+        w->n_rec++;
+        w->c.improvements++;
+    } else if (s->r == w->best_rank && (uint64_t)g[0] < prm->t_eq) {
+        w->best = *s;
+        w->c.eq_accepts++;
+    }
+    /* reduce with probability p_reduce: merge the modified terms */
+    if ((uint64_t)g[1] < prm->t_reduce) w->c.merges += reduce_tracked(s, track, 2);
+    /* expand with probability p_expand, only near the best rank */
+    if ((uint64_t)g[2] < prm->t_expand && s->r <= w->best_rank + 2 && s->r < prm->r_cap)
+        expand(w, prm, t);
+    restart_check(w, prm, t);
+}
+
+void or_walk_run(or_walk *w, const or_params *prm, int64_t n_iters)
+{
+    for (int64_t step = 0; step < n_iters; ++step) {
+        if (w->best_rank <= prm->target_rank) w->done = 1;
+        if (w->done || w->t >= prm->max_iters) return;
+        int64_t t = w->t + 1;
+        one_iteration(w, prm, t);
+        w->t = t;
+    }
+    if (w->best_rank <= prm->target_rank) w->done = 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Many walks on host threads (used to time the oracle)                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const or_scheme *start;
+    const or_params *prm;
+    uint64_t base_seed;
+    int64_t first_walk;
+    int n_walks;
+    int64_t n_iters;
+    or_walk *out;
+    int next;
+    pthread_mutex_t lock;
+} many_job;
+
+static void *many_worker(void *arg)
+{
+    many_job *job = (many_job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&job->lock);
+        int k = job->next++;
+        pthread_mutex_unlock(&job->lock);
+        if (k >= job->n_walks) break;
+        or_params prm = *job->prm;
+        prm.seed = job->base_seed + (uint64_t)(job->first_walk + k);
+        or_walk_init(&job->out[k], job->start);
+        or_walk_run(&job->out[k], &prm, job->n_iters);
+    }
+    return NULL;
+}
+
+void or_run_many(const or_scheme *start, const or_params *prm, uint64_t base_seed,
+                 int64_t first_walk, int n_walks, int64_t n_iters, int n_threads,
+                 or_walk *out)
+{
+    many_job job;
+    job.start = start; job.prm = prm; job.base_seed = base_seed;
+    job.first_walk = first_walk; job.n_walks = n_walks; job.n_iters = n_iters;
+    job.out = out; job.next = 0;
+    pthread_mutex_init(&job.lock, NULL);
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    pthread_t th[256];
+    for (int q = 0; q < n_threads; ++q) pthread_create(&th[q], NULL, many_worker, &job);
+    for (int q = 0; q < n_threads; ++q) pthread_join(th[q], NULL);
+    pthread_mutex_destroy(&job.lock);
+}
