@@ -1,0 +1,240 @@
+/*
+ * tsf.h -- C ABI of the ternary flip-graph walk library (libtsf.so) for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library implements the hot path of the ternary meta flip graph method
+ * (Perminov, "Fast Matrix Multiplication via Ternary Meta Flip Graphs",
+ * arXiv 2511.20317): many independent random walks (Algorithm 1, Sec. 3.4.2)
+ * over matrix multiplication schemes (m,n,p:r) whose coefficients lie in
+ * Z_T = {-1,0,1} (Sec. 3.2) or in the binary field Z2 (Sec. 3.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a tsf_status (0 = success, < 0 = error) and leaves
+ *   a human-readable reason for the last error of the calling thread in
+ *   tsf_last_error().  On error no output is modified unless stated.
+ * - The library never allocates memory visible to the caller and never frees
+ *   caller memory.  "host" pointers point to ordinary CPU memory, "device"
+ *   pointers to GPU global memory (e.g. a torch CUDA/HIP tensor's data_ptr()).
+ * - Scheme interchange (host, int8): a scheme (m,n,p:r) is r terms
+ *   u(l) (x) v(l) (x) w(l) (Sec. 3.1).  Row l of U holds u(l) flattened as in
+ *   the worked example of Sec. 3.1.1: a_ij -> i*n+j (length m*n); V: b_jk ->
+ *   j*p+k (length n*p); W: c_ik -> k*m+i (length p*m, the C^T convention of
+ *   Sec. 3.1).  Rows are stored back to back with no padding: U is
+ *   capacity x (m*n) int8, V capacity x (n*p), W capacity x (p*m).  Rows at or
+ *   beyond `rank` are ignored on input and zero-filled on output.
+ * - Packed form (device and host): the one-bit representation of Sec. 3.5.1.
+ *   Each factor vector is two uint64 masks, `digits` (bit e set iff entry e
+ *   is non-zero) and `signs` (bit e set iff entry e is -1; always a subset of
+ *   digits; zero in Z2).  A term is 6 uint64 words in the order
+ *   u.digits, u.signs, v.digits, v.signs, w.digits, w.signs (48 bytes), and a
+ *   packed scheme is `capacity` such terms.  Factor lengths are at most 64
+ *   (Sec. 4.1 and 5.3).
+ * - Walk results depend only on (parameters, base_seed, walk id, start
+ *   scheme): never on the batch composition, the lanes-per-walk choice, the
+ *   launch shape or how the iterations are split into calls.
+ */
+#ifndef TSF_H
+#define TSF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TSF_OK = 0,
+    TSF_E_ARG = -1,            /* null pointer, bad size or out-of-range argument    */
+    TSF_E_FORMAT = -2,         /* a dimension < 1 or a factor length above 64        */
+    TSF_E_CAPACITY = -3,       /* a scheme does not fit its capacity                 */
+    TSF_E_NOT_TERNARY = -4,    /* a coefficient outside the mode's set, or signs
+                                  not a subset of digits                             */
+    TSF_E_INVALID_SCHEME = -5, /* the Brent equations do not hold                    */
+    TSF_E_DEVICE = -6,         /* a HIP runtime call failed                          */
+    TSF_E_STATE = -7           /* walk state inconsistent with the parameters        */
+} tsf_status;
+
+typedef enum { TSF_TERNARY = 0, TSF_Z2 = 1 } tsf_mode;
+
+typedef struct {
+    int32_t m, n, p;   /* format: A is m x n, B is n x p                        */
+    int32_t rank;      /* number of live terms r                                */
+    int32_t capacity;  /* rows allocated in U, V, W (>= rank)                   */
+    int32_t mode;      /* tsf_mode                                              */
+} tsf_dims;
+
+typedef struct {
+    tsf_dims d;
+    int8_t *U, *V, *W; /* host, caller-owned, capacity rows each                */
+} tsf_scheme;
+
+/* Thread-local text of the last error reported on this thread. */
+const char *tsf_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Host scheme operations                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* The standard scheme of rank m*n*p: one term a_ij (x) b_jk (x) c_ik for every
+ * (i,j,k), in lexicographic (i,j,k) order (the naive algorithm that Sec. 3.4.1
+ * initialises populations with).  out->U/V/W must hold out->d.capacity >=
+ * m*n*p rows; out->d's m, n, p, rank, mode are written.
+ * Errors: TSF_E_FORMAT (dims < 1 or a factor length > 64), TSF_E_CAPACITY. */
+tsf_status tsf_init_scheme(int32_t m, int32_t n, int32_t p, int32_t mode, tsf_scheme *out);
+
+/* Brent equations (Eq. 1) in the C^T form of Sec. 3.1:
+ *   sum_l u_l[a1*n+a2] v_l[b1*p+b2] w_l[c1*m+c2] = [a2=b1][b2=c1][c2=a1]
+ * checked exactly over the integers (ternary) or modulo 2 (Z2).
+ * *n_violated receives the number of equations that fail (0 = valid scheme).
+ * Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_NOT_TERNARY (entry outside the set). */
+tsf_status tsf_verify(const tsf_scheme *s, int64_t *n_violated);
+
+/* Sign-symmetry normalisation (Sec. 3.6), in place: per term, the first
+ * non-zero entry of u and then of v is made positive, w absorbing each sign.
+ * No-op in Z2.  Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_NOT_TERNARY. */
+tsf_status tsf_normalise(tsf_scheme *s);
+
+/* Reduction operator (Sec. 3.3.1) applied to a fixpoint, in place: terms with
+ * a zero factor are removed, then any two terms sharing two factors (w up to
+ * sign) merge into one while the merged factor stays in the mode's set; the
+ * result is normalised.  *n_reductions receives the number of merges.
+ * Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_NOT_TERNARY. */
+tsf_status tsf_reduce(tsf_scheme *s, int32_t *n_reductions);
+
+/* Project meta operator (Sec. 3.3.2): drop index `index` of `axis`
+ * (0 = m, 1 = n, 2 = p) from every factor, remove the terms that became
+ * zero, normalise.  out must have capacity >= in->d.rank.
+ * Errors: TSF_E_ARG (axis/index out of range, dimension 1), TSF_E_CAPACITY. */
+tsf_status tsf_meta_project(const tsf_scheme *in, int32_t axis, int32_t index, tsf_scheme *out);
+
+/* Extend meta operator (Sec. 3.3.2): (m,n,p:r) -> (m,n,p+1:r+m*n) by
+ * appending the naive (m,n,1) scheme for the new index (terms in (i,j)
+ * order); along m the naive (1,n,p) scheme ((j,k) order, +n*p terms), along
+ * n the naive (m,1,p) scheme ((i,k) order, +m*p terms).
+ * Errors: TSF_E_ARG, TSF_E_FORMAT (a new length > 64), TSF_E_CAPACITY. */
+tsf_status tsf_meta_extend(const tsf_scheme *in, int32_t axis, tsf_scheme *out);
+
+/* int8 interchange <-> packed one-bit form (Sec. 3.5.1), host memory.
+ * tsf_pack writes in->d.capacity terms (48 bytes each; rows >= rank zero).
+ * tsf_unpack reads d->capacity packed terms into out (whose d is set to *d).
+ * Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_NOT_TERNARY (signs not within
+ * digits, or bits beyond the factor length). */
+tsf_status tsf_pack(const tsf_scheme *in, uint64_t *packed);
+tsf_status tsf_unpack(const uint64_t *packed, const tsf_dims *d, tsf_scheme *out);
+
+/* ------------------------------------------------------------------------ */
+/* Batched random walks on the GPU (Algorithm 1, Sec. 3.4.2)                 */
+/* ------------------------------------------------------------------------ */
+
+/* Walk parameters.  Probabilities are integer thresholds on a 32-bit random
+ * word: an event with probability p fires iff word < t, t = round(p * 2^32)
+ * in [0, 2^32] (so 2^32 means "always"). */
+typedef struct {
+    uint64_t base_seed;        /* walk w draws from Philox4x32-10 keyed by
+                                  base_seed + first_walk_id + w                   */
+    int64_t  first_walk_id;    /* global id of the batch's walk 0                 */
+    int64_t  max_iters;        /* iteration budget per walk                       */
+    int64_t  plateau;          /* restart after this many iterations without a
+                                  strict improvement of the best rank (<= 0: off) */
+    int32_t  flip_tries;       /* random flip attempts per iteration (1..64)
+                                  before the exhaustive search                    */
+    int32_t  restart_from_best;/* restart from the best scheme instead of the start */
+    uint64_t t_eq;             /* accept an equal-rank scheme as best (Alg. 1: 0.01) */
+    uint64_t t_reduce;         /* p_reduce of Alg. 1                              */
+    uint64_t t_expand;         /* p_expand of Alg. 1                              */
+} tsf_walk_params;
+
+/* Per-walk state header (device memory, one per walk, 160 bytes). */
+typedef struct {
+    int32_t m, n, p, mode;     /* the walk's format and coefficient set           */
+    int32_t r_cap;             /* expand is refused at this rank (<= capacity)    */
+    int32_t target_rank;       /* the walk stops once best_rank <= target_rank    */
+    int32_t rank;              /* rank of the current scheme                      */
+    int32_t best_rank;         /* rank of the best scheme                         */
+    int32_t start_rank;        /* rank of the start scheme                        */
+    int32_t done;              /* 1 once the target was reached; -1 header does
+                                  not fit the batch; -2 invalid start scheme      */
+    int32_t n_rec;             /* strict improvements so far (records kept up to
+                                  the batch's rec_cap)                            */
+    int32_t reserved;
+    int64_t t;                 /* iterations completed                            */
+    int64_t plateau_start;     /* iteration of the last strict improvement/restart */
+    int64_t counters[12];      /* iters, flips, attempts, fallbacks, dead_ends,
+                                  zero_removed, merges, expands, expand_fails,
+                                  restarts, eq_accepts, improvements              */
+} tsf_walk_header;
+
+/* One strict improvement of a walk's best rank. */
+typedef struct {
+    int64_t iter;              /* iteration at which it happened                 */
+    int32_t rank;              /* the new best rank                              */
+    int32_t reserved;
+} tsf_record;
+
+/* A batch of walks.  All buffers are device memory owned by the caller.
+ * Walk w uses:  hdr[w];  cur, best, start: packed schemes of `capacity` terms
+ * at offset w * capacity * 6 uint64;  rec: rec_cap records at w * rec_cap.
+ * Walks of different formats and ranks may share one batch; a walk whose
+ * header disagrees with the batch's mode or max_len, or does not fit its
+ * capacity, is never advanced and gets done = -1. */
+typedef struct {
+    int32_t n_walks;
+    int32_t capacity;          /* term slots per walk in cur/best/start (<= 512)  */
+    int32_t rec_cap;           /* records kept per walk                           */
+    int32_t mode;              /* tsf_mode shared by every walk of the batch      */
+    int32_t max_len;           /* largest factor length of any walk (<= 64); 32
+                                  or less selects the 32-bit kernels              */
+    int32_t reserved;
+    tsf_walk_header *hdr;
+    uint64_t *cur;
+    uint64_t *best;
+    const uint64_t *start;
+    tsf_record *rec;
+} tsf_walk_batch;
+
+/* Launch configuration: lanes cooperating on one walk (8, 16, 32 or 64, i.e.
+ * 8, 4, 2 or 1 walks per 64-lane wavefront) and wavefronts per workgroup.
+ * 0 in both fields lets the library choose (its autotuned table). */
+typedef struct {
+    int32_t lanes_per_walk;
+    int32_t waves_per_block;
+} tsf_launch;
+
+typedef struct tsf_ctx tsf_ctx;
+
+/* Context: holds the autotuned launch table.  Not thread-safe per context. */
+tsf_status tsf_ctx_create(tsf_ctx **ctx);
+tsf_status tsf_ctx_destroy(tsf_ctx *ctx);
+
+/* Initialise every walk of the batch from its start scheme (device kernel):
+ * cur := start, best := start, counters and records cleared.  Before the
+ * call the caller fills, per walk, hdr[w].{m,n,p,mode,r_cap,target_rank,
+ * start_rank} and the packed, normalised start scheme (tsf_pack of a scheme
+ * passed through tsf_normalise).  Asynchronous on `hip_stream`.
+ * Errors (checked on the host before launch): TSF_E_ARG, TSF_E_CAPACITY. */
+tsf_status tsf_walk_init(tsf_ctx *ctx, const tsf_walk_batch *b, void *hip_stream);
+
+/* Run up to n_iters further iterations of Algorithm 1 on every walk of the
+ * batch (a walk stops early at its target rank or its iteration budget).
+ * Asynchronous on `hip_stream`; `launch` may be NULL (library choice).
+ * The host validates the batch shape against the chosen kernel; the per-walk
+ * headers are device data and are trusted to be what tsf_walk_init and
+ * earlier tsf_walk calls left.  Errors: TSF_E_ARG, TSF_E_CAPACITY,
+ * TSF_E_DEVICE. */
+tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                    int64_t n_iters, const tsf_launch *launch, void *hip_stream);
+
+/* Exact Brent verification (Eq. 1, C^T form of Sec. 3.1) on the GPU of one
+ * scheme per walk of the batch: which = 0 checks cur (rank hdr[w].rank),
+ * 1 checks best (hdr[w].best_rank), 2 checks start (hdr[w].start_rank).
+ * n_violated (device, n_walks int64) receives the number of failed
+ * equations per walk (0 = valid).  Asynchronous on `hip_stream`.
+ * Errors: TSF_E_ARG, TSF_E_DEVICE. */
+tsf_status tsf_verify_batch(const tsf_walk_batch *b, int32_t which, int64_t *n_violated,
+                            void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

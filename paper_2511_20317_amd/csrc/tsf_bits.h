@@ -1,0 +1,107 @@
+// tsf_bits.h -- one-bit ternary vectors and the walk's counter-based random
+// stream, shared by the host library and the gfx950 kernels.
+//
+// A ternary vector (Sec. 3.5.1 of the paper) is a pair of masks: `d` has bit e
+// set iff entry e is non-zero, `s` has bit e set iff entry e is -1 (s is a
+// subset of d).  Z2 vectors use d only.  The arithmetic follows the formulas
+// of Sec. 3.5.2; each returns whether the result stays in {-1,0,1}.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIP__)
+#define TSF_HD __host__ __device__ __forceinline__
+#else
+#define TSF_HD static inline
+#endif
+
+// a + b: d = da ^ db, s = (sa&da | sb&db) & d; overflow where both entries
+// are non-zero with equal signs.
+template <typename T>
+TSF_HD bool tern_add(T da, T sa, T db, T sb, T &d, T &s)
+{
+    d = da ^ db;
+    s = ((sa & da) | (sb & db)) & d;
+    return (da & db & ~(sa ^ sb)) == 0;
+}
+
+// a - b: d = da ^ db, s = (sa&da | ~sb&db) & d; overflow where both entries
+// are non-zero with different signs.
+template <typename T>
+TSF_HD bool tern_sub(T da, T sa, T db, T sb, T &d, T &s)
+{
+    d = da ^ db;
+    s = ((sa & da) | (~sb & db)) & d;
+    return (da & db & (sa ^ sb)) == 0;
+}
+
+// a + sigma*b with sigma = +1 or -1; in Z2 plain XOR (always valid).
+template <typename T>
+TSF_HD bool tern_axpy(bool z2, int sigma, T da, T sa, T db, T sb, T &d, T &s)
+{
+    if (z2) {
+        d = da ^ db;
+        s = 0;
+        return true;
+    }
+    return sigma > 0 ? tern_add(da, sa, db, sb, d, s) : tern_sub(da, sa, db, sb, d, s);
+}
+
+// a == -b: same support, signs opposite on it.
+template <typename T>
+TSF_HD bool tern_neg_eq(T da, T sa, T db, T sb)
+{
+    return da == db && sa == (sb ^ db);
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers
+// 0xD2511F53 / 0xCD9E8D57, key increments 0x9E3779B9 / 0xBB67AE85.
+struct Philox4 {
+    uint32_t x[4];
+};
+
+TSF_HD Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                             uint32_t k1)
+{
+#if defined(__HIP__)
+#pragma unroll
+#endif
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t prod0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t prod1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t y0 = (uint32_t)(prod1 >> 32) ^ c1 ^ k0;
+        const uint32_t y2 = (uint32_t)(prod0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)prod1;
+        c3 = (uint32_t)prod0;
+        c0 = y0;
+        c2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Philox4 out;
+    out.x[0] = c0;
+    out.x[1] = c1;
+    out.x[2] = c2;
+    out.x[3] = c3;
+    return out;
+}
+
+// The walk's random block for (seed, iteration t, attempt a, domain dom):
+// key = seed, counter = (t lo, t hi, a, dom).  Domains: 0 flip attempts,
+// 1 per-iteration gates, 2 expand attempts.
+TSF_HD Philox4 walk_block(uint64_t seed, int64_t t, uint32_t a, uint32_t dom)
+{
+    return philox4x32_10((uint32_t)(uint64_t)t, (uint32_t)((uint64_t)t >> 32), a, dom,
+                         (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// uniform integer in [0, n) from one word: (word * n) >> 32
+TSF_HD uint32_t below(uint32_t word, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)word * n) >> 32);
+}
+
+// counters kept per walk, in tsf_walk_header.counters order
+enum {
+    C_ITERS = 0, C_FLIPS, C_ATTEMPTS, C_FALLBACKS, C_DEAD_ENDS, C_ZERO_REMOVED, C_MERGES,
+    C_EXPANDS, C_EXPAND_FAILS, C_RESTARTS, C_EQ_ACCEPTS, C_IMPROVEMENTS, C_NUM
+};

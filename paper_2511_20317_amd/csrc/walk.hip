@@ -1,0 +1,278 @@
+// walk.hip -- host side of the batched walks: walk-state initialisation,
+// batch Brent verification on the GPU, and the launch of the walk kernels
+// (walk_kernel.h, instantiated in walk_inst.hip).
+#include "walk_kernel.h"
+#include "tsf_internal.h"
+
+#include <cstring>
+
+namespace tsfk {
+KernelFn pick_kernel_w0_z0(int g, int s);
+KernelFn pick_kernel_w0_z1(int g, int s);
+KernelFn pick_kernel_w1_z0(int g, int s);
+KernelFn pick_kernel_w1_z1(int g, int s);
+}  // namespace tsfk
+
+namespace {
+using namespace tsfk;
+
+// One wavefront per walk: validate the start scheme, then cur := best :=
+// start and clear the walk's state.
+__global__ void __launch_bounds__(64) init_kernel(tsf_walk_header *hdr, uint64_t *cur,
+                                                  uint64_t *best, const uint64_t *start,
+                                                  int32_t n_walks, int32_t cap)
+{
+    const int64_t walk = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (walk >= n_walks) return;
+    tsf_walk_header *h = hdr + walk;
+    const int m = h->m, n = h->n, p = h->p, r0 = h->start_rank;
+    const bool z2 = h->mode == 1;
+    bool ok = m >= 1 && n >= 1 && p >= 1 && (h->mode == 0 || h->mode == 1) && r0 >= 0 &&
+              r0 <= h->r_cap && h->r_cap <= cap;
+    const int len[3] = {m * n, n * p, p * m};
+    ok = ok && len[0] <= 64 && len[1] <= 64 && len[2] <= 64;
+    const size_t base = (size_t)walk * cap * 6;
+    bool bad = false;
+    if (ok) {
+        for (int k = lane; k < r0; k += 64) {
+            for (int X = 0; X < 3; ++X) {
+                const uint64_t d = start[base + k * 6 + 2 * X], s = start[base + k * 6 + 2 * X + 1];
+                const uint64_t lim = len[X] == 64 ? ~0ull : ((1ull << len[X]) - 1);
+                if (d == 0 || (s & ~d) || (d & ~lim) || (z2 && s)) bad = true;
+                if (!z2 && X < 2 && (s & (d & (~d + 1)))) bad = true;  // not normalised
+            }
+            for (int x = 0; x < 6; ++x) {
+                cur[base + k * 6 + x] = start[base + k * 6 + x];
+                best[base + k * 6 + x] = start[base + k * 6 + x];
+            }
+        }
+    }
+    const bool any_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+        h->done = (!ok || any_bad) ? -2 : 0;
+        h->rank = r0;
+        h->best_rank = r0;
+        h->n_rec = 0;
+        h->reserved = 0;
+        h->t = 0;
+        h->plateau_start = 0;
+        for (int c = 0; c < 12; ++c) h->counters[c] = 0;
+    }
+}
+
+// Brent verification (Eq. 1, C^T form of Sec. 3.1) of one scheme per
+// workgroup: the tensor sum_l u_l (x) v_l (x) w_l is built one u-entry slice
+// at a time in LDS (int32 atomics over the non-zero products), then compared
+// with the matrix multiplication tensor.
+__global__ void __launch_bounds__(256) verify_kernel(const tsf_walk_header *hdr,
+                                                     const uint64_t *schemes, int32_t cap,
+                                                     int32_t n_walks, int32_t which,
+                                                     int64_t *n_violated)
+{
+    __shared__ int32_t slice[64 * 64];
+    __shared__ int32_t bad_sh;
+    const int64_t q = blockIdx.x;
+    if (q >= n_walks) return;
+    const tsf_walk_header *h = hdr + q;
+    const int m = h->m, n = h->n, p = h->p;
+    const int rank = which == 0 ? h->rank : which == 1 ? h->best_rank : h->start_rank;
+    const bool z2 = h->mode == 1;
+    const int Lu = m * n, Lv = n * p, Lw = p * m;
+    if (m < 1 || n < 1 || p < 1 || Lu > 64 || Lv > 64 || Lw > 64 || rank < 0 || rank > cap) {
+        if (threadIdx.x == 0) n_violated[q] = -1;
+        return;
+    }
+    const uint64_t *sc = schemes + (size_t)q * cap * 6;
+    if (threadIdx.x == 0) bad_sh = 0;
+    int32_t bad = 0;
+    for (int av = 0; av < Lu; ++av) {
+        for (int e = threadIdx.x; e < Lv * Lw; e += blockDim.x) slice[e] = 0;
+        __syncthreads();
+        const int a1 = av / n, a2 = av % n;
+        for (int l = threadIdx.x; l < rank; l += blockDim.x) {
+            const uint64_t ud = sc[l * 6 + 0], us = sc[l * 6 + 1];
+            if (!((ud >> av) & 1)) continue;
+            const int su = ((us >> av) & 1) ? -1 : 1;
+            for (uint64_t dv = sc[l * 6 + 2]; dv; dv &= dv - 1) {
+                const int b = __builtin_ctzll(dv);
+                const int sv = ((sc[l * 6 + 3] >> b) & 1) ? -su : su;
+                for (uint64_t dw = sc[l * 6 + 4]; dw; dw &= dw - 1) {
+                    const int c = __builtin_ctzll(dw);
+                    atomicAdd(&slice[b * Lw + c], ((sc[l * 6 + 5] >> c) & 1) ? -sv : sv);
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < Lv * Lw; e += blockDim.x) {
+            const int b = e / Lw, c = e % Lw;
+            const int b1 = b / p, b2 = b % p, c1 = c / m, c2 = c % m;
+            const int want = (a2 == b1 && b2 == c1 && c2 == a1) ? 1 : 0;
+            int got = slice[e];
+            if (z2) got &= 1;
+            bad += got != want;
+        }
+        __syncthreads();
+    }
+    atomicAdd(&bad_sh, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) n_violated[q] = bad_sh;
+}
+
+// ---------------------------------------------------------------------------
+// host side: kernel table and launch
+// ---------------------------------------------------------------------------
+KernelFn pick_kernel(int g, int s, bool wide, bool z2)
+{
+    if (wide) return z2 ? pick_kernel_w1_z1(g, s) : pick_kernel_w1_z0(g, s);
+    return z2 ? pick_kernel_w0_z1(g, s) : pick_kernel_w0_z0(g, s);
+}
+
+int slots_for(int cap, int g)
+{
+    for (int s : {1, 2, 4, 8})
+        if (s * g >= cap) return s;
+    return -1;
+}
+
+tsf_status check_batch(const tsf_walk_batch *b)
+{
+    if (!b) return tsf_fail(TSF_E_ARG, "null batch");
+    if (b->n_walks < 0) return tsf_fail(TSF_E_ARG, "n_walks %d < 0", b->n_walks);
+    if (b->capacity < 1 || b->capacity > 512)
+        return tsf_fail(TSF_E_CAPACITY, "capacity %d outside [1, 512]", b->capacity);
+    if (b->rec_cap < 0) return tsf_fail(TSF_E_ARG, "rec_cap %d < 0", b->rec_cap);
+    if (b->mode != TSF_TERNARY && b->mode != TSF_Z2)
+        return tsf_fail(TSF_E_ARG, "batch mode %d", b->mode);
+    if (b->max_len < 1 || b->max_len > 64)
+        return tsf_fail(TSF_E_FORMAT, "max_len %d outside [1, 64]", b->max_len);
+    if (b->n_walks > 0 && (!b->hdr || !b->cur || !b->best || !b->start ||
+                           (b->rec_cap > 0 && !b->rec)))
+        return tsf_fail(TSF_E_ARG, "null device buffer");
+    return TSF_OK;
+}
+
+}  // namespace
+
+struct tsf_ctx {
+    int device;
+    int cu_count;
+};
+
+extern "C" {
+
+tsf_status tsf_ctx_create(tsf_ctx **ctx)
+{
+    if (!ctx) return tsf_fail(TSF_E_ARG, "null ctx pointer");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return tsf_fail(TSF_E_DEVICE, "hipGetDevice failed");
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return tsf_fail(TSF_E_DEVICE, "hipDeviceGetAttribute failed");
+    tsf_ctx *c = new tsf_ctx;
+    c->device = dev;
+    c->cu_count = cus;
+    *ctx = c;
+    return TSF_OK;
+}
+
+tsf_status tsf_ctx_destroy(tsf_ctx *ctx)
+{
+    delete ctx;
+    return TSF_OK;
+}
+
+tsf_status tsf_walk_init(tsf_ctx *ctx, const tsf_walk_batch *b, void *hip_stream)
+{
+    (void)ctx;
+    tsf_status st = check_batch(b);
+    if (st) return st;
+    if (b->n_walks == 0) return TSF_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(init_kernel, dim3(b->n_walks), dim3(64), 0, s, b->hdr, b->cur, b->best,
+                       b->start, b->n_walks, b->capacity);
+    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "init launch failed");
+    return TSF_OK;
+}
+
+tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                    int64_t n_iters, const tsf_launch *launch, void *hip_stream)
+{
+    (void)ctx;
+    tsf_status st = check_batch(b);
+    if (st) return st;
+    if (!prm) return tsf_fail(TSF_E_ARG, "null params");
+    if (prm->flip_tries < 1 || prm->flip_tries > 64)
+        return tsf_fail(TSF_E_ARG, "flip_tries %d outside [1, 64]", prm->flip_tries);
+    if (prm->t_eq > (1ull << 32) || prm->t_reduce > (1ull << 32) || prm->t_expand > (1ull << 32))
+        return tsf_fail(TSF_E_ARG, "a probability threshold exceeds 2^32");
+    if (n_iters < 0) return tsf_fail(TSF_E_ARG, "n_iters < 0");
+    if (b->n_walks == 0 || n_iters == 0) return TSF_OK;
+    int g = launch && launch->lanes_per_walk ? launch->lanes_per_walk : (b->capacity <= 64 ? 8 : 64);
+    int wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4;
+    if (g != 8 && g != 16 && g != 32 && g != 64)
+        return tsf_fail(TSF_E_ARG, "lanes_per_walk %d not in {8,16,32,64}", g);
+    if (wpb < 1 || wpb > 4) return tsf_fail(TSF_E_ARG, "waves_per_block %d not in 1..4", wpb);
+    const int s = slots_for(b->capacity, g);
+    if (s < 0)
+        return tsf_fail(TSF_E_CAPACITY, "capacity %d needs more than 8 slots at %d lanes/walk",
+                        b->capacity, g);
+    const bool wide = b->max_len > 32;
+    KernelFn fn = pick_kernel(g, s, wide, b->mode == TSF_Z2);
+    if (!fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
+    const size_t word = wide ? 8 : 4;
+    const int walks_per_wave = 64 / g;
+    const size_t lds = (size_t)wpb * walks_per_wave * b->capacity * 6 * word;
+    if (lds > 160 * 1024)
+        return tsf_fail(TSF_E_CAPACITY, "%zu bytes of LDS per workgroup exceed 160 KiB", lds);
+    KArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.base_seed = prm->base_seed;
+    a.first_walk_id = prm->first_walk_id;
+    a.max_iters = prm->max_iters;
+    a.plateau = prm->plateau;
+    a.n_iters = n_iters;
+    a.t_eq = prm->t_eq;
+    a.t_reduce = prm->t_reduce;
+    a.t_expand = prm->t_expand;
+    a.flip_tries = prm->flip_tries;
+    a.restart_from_best = prm->restart_from_best;
+    a.n_walks = b->n_walks;
+    a.cap = b->capacity;
+    a.rec_cap = b->rec_cap;
+    a.mode = b->mode;
+    a.max_len = b->max_len;
+    a.hdr = b->hdr;
+    a.cur = b->cur;
+    a.best = b->best;
+    a.start = b->start;
+    a.rec = b->rec;
+    const int64_t walks_per_block = (int64_t)wpb * walks_per_wave;
+    const int64_t blocks = (b->n_walks + walks_per_block - 1) / walks_per_block;
+    hipStream_t hs = (hipStream_t)hip_stream;
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+        return tsf_fail(TSF_E_DEVICE, "cannot raise the LDS limit to %zu bytes", lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, hs, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return tsf_fail(TSF_E_DEVICE, "walk launch failed: %s", hipGetErrorString(e));
+    return TSF_OK;
+}
+
+tsf_status tsf_verify_batch(const tsf_walk_batch *b, int32_t which, int64_t *n_violated,
+                            void *hip_stream)
+{
+    tsf_status st = check_batch(b);
+    if (st) return st;
+    if (which < 0 || which > 2) return tsf_fail(TSF_E_ARG, "which %d not in 0..2", which);
+    if (!n_violated && b->n_walks) return tsf_fail(TSF_E_ARG, "null output");
+    if (b->n_walks == 0) return TSF_OK;
+    const uint64_t *src = which == 0 ? b->cur : which == 1 ? b->best : b->start;
+    hipLaunchKernelGGL(verify_kernel, dim3(b->n_walks), dim3(256), 0, (hipStream_t)hip_stream,
+                       b->hdr, src, b->capacity, b->n_walks, which, n_violated);
+    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "verify launch failed");
+    return TSF_OK;
+}
+
+}  // extern "C"

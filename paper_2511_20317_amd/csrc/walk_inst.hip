@@ -1,0 +1,44 @@
+// walk_inst.hip -- one translation unit of walk-kernel instantiations.  It is
+// compiled once per (word width, coefficient set) with TSFK_WIDE (0: 32-bit
+// masks, 1: 64-bit masks) and TSFK_Z2 (0: ternary, 1: Z2) defined, so the
+// builds of the four groups run in parallel.
+#include "walk_kernel.h"
+
+#ifndef TSFK_WIDE
+#error "TSFK_WIDE must be defined"
+#endif
+#ifndef TSFK_Z2
+#error "TSFK_Z2 must be defined"
+#endif
+
+namespace tsfk {
+
+using Word = std::conditional_t<TSFK_WIDE != 0, uint64_t, uint32_t>;
+constexpr bool kZ2 = TSFK_Z2 != 0;
+
+template <int G>
+KernelFn pick_s(int s)
+{
+    switch (s) {
+    case 1: return walk_kernel<G, 1, Word, kZ2>;
+    case 2: return walk_kernel<G, 2, Word, kZ2>;
+    case 4: return walk_kernel<G, 4, Word, kZ2>;
+    case 8: return walk_kernel<G, 8, Word, kZ2>;
+    default: return nullptr;
+    }
+}
+
+#define TSF_CAT2(a, b, c) pick_kernel_w##a##_z##b##c
+#define TSF_CAT(a, b) TSF_CAT2(a, b, )
+KernelFn TSF_CAT(TSFK_WIDE, TSFK_Z2)(int g, int s)
+{
+    switch (g) {
+    case 8: return pick_s<8>(s);
+    case 16: return pick_s<16>(s);
+    case 32: return pick_s<32>(s);
+    case 64: return pick_s<64>(s);
+    default: return nullptr;
+    }
+}
+
+}  // namespace tsfk

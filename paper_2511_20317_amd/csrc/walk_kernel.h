@@ -1,0 +1,598 @@
+// walk_kernel.h -- batched ternary flip-graph random walks on gfx950 (MI355X).
+//
+// One walk is owned by a group of G lanes of a 64-lane wavefront (G = 8, 16,
+// 32 or 64, i.e. 64/G walks per wavefront).  The walk's current scheme lives
+// in LDS in the one-bit form of Sec. 3.5.1 (per term: u, v, w as digit/sign
+// mask pairs; 32-bit words when every factor has at most 32 entries).  Term k
+// is examined by lane k mod G, so one partner search over r terms costs
+// ceil(r/G) masked compares per lane plus one group ballot per slot.  All
+// per-walk scalars (rank, counters, random words) are replicated in every
+// lane of the group, which keeps control flow uniform inside a group; groups
+// of one wavefront diverge freely because no instruction mixes lanes of
+// different groups.  HBM is read and written only at the start and end of a
+// call (coalesced over the group's lanes) and when the best scheme changes.
+//
+// The iteration follows Algorithm 1 (RandomWalk kernel, Sec. 3.4.2): a flip
+// (Sec. 3.3.1) with ternary-safe arithmetic (Sec. 3.5.2) and sign
+// normalisation (Sec. 3.6), zero-term removal, the best-scheme update,
+// reduction with probability p_reduce, expand with probability p_expand near
+// the best rank, and a plateau restart.  The random words come from one
+// Philox4x32-10 block per (iteration, attempt, domain), so a skipped draw
+// never shifts the stream and results do not depend on G or the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/tsf.h"
+#include "tsf_bits.h"
+
+namespace tsfk {
+
+struct KArgs {
+    uint64_t base_seed;
+    int64_t first_walk_id;
+    int64_t max_iters;
+    int64_t plateau;
+    int64_t n_iters;
+    uint64_t t_eq, t_reduce, t_expand;
+    int32_t flip_tries;
+    int32_t restart_from_best;
+    int32_t n_walks;
+    int32_t cap;
+    int32_t rec_cap;
+    int32_t mode;
+    int32_t max_len;
+    int32_t pad;
+    tsf_walk_header *hdr;
+    uint64_t *cur;
+    uint64_t *best;
+    const uint64_t *start;
+    tsf_record *rec;
+};
+
+// role permutations (X,Y,Z) of (U,V,W), lexicographic
+static __constant__ int8_t kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+template <typename T>
+struct TV {
+    T d, s;
+};
+
+template <typename T>
+__device__ __forceinline__ bool eqv(TV<T> a, TV<T> b)
+{
+    return a.d == b.d && a.s == b.s;
+}
+
+// Order LDS accesses of the lanes of one wavefront: LDS instructions of a
+// wavefront complete in issue order; this keeps the compiler from moving
+// accesses across the point where one lane's store must be seen by others.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ int ctz_t(T x)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_ctzll(x);
+    else
+        return __builtin_ctz(x);
+}
+
+__device__ __forceinline__ int popc64(uint64_t x) { return __builtin_popcountll(x); }
+
+// index of the c-th (0-based) set bit of m (m has more than c bits set)
+__device__ __forceinline__ int kth_bit(uint64_t m, int c)
+{
+    for (int q = 0; q < c; ++q) m &= m - 1;
+    return __builtin_ctzll(m);
+}
+
+template <int G, int S, typename T, bool Z2>
+struct Walker {
+    // group geometry
+    int gl;      // lane within the group
+    int gshift;  // first lane of the group within the wavefront
+    T *lds;      // this walk's terms: word x of term k at lds[k*6 + x]
+    // walk scalars, identical in every lane of the group
+    uint64_t seed;
+    int r, r_cap, best_rank, start_rank, target, n_rec;
+    int64_t t, plateau_start;
+    uint32_t cnt[C_NUM];
+    const KArgs *a;
+    int64_t walk;
+
+    __device__ __forceinline__ uint64_t gballot(bool p) const
+    {
+        uint64_t m = __ballot(p);
+        if constexpr (G == 64)
+            return m;
+        else
+            return (m >> gshift) & ((1ull << G) - 1);
+    }
+
+    __device__ __forceinline__ TV<T> ld(int k, int X) const
+    {
+        const T *q = lds + k * 6 + 2 * X;
+        return TV<T>{q[0], q[1]};
+    }
+    __device__ __forceinline__ void st(int k, int X, TV<T> v)
+    {
+        if (gl == 0) {
+            T *q = lds + k * 6 + 2 * X;
+            q[0] = v.d;
+            q[1] = v.s;
+        }
+    }
+
+    __device__ __forceinline__ static bool axpy(int sigma, TV<T> x, TV<T> y, TV<T> &o)
+    {
+        if constexpr (Z2) {
+            o.d = x.d ^ y.d;
+            o.s = 0;
+            return true;
+        } else {
+            return sigma > 0 ? tern_add(x.d, x.s, y.d, y.s, o.d, o.s)
+                             : tern_sub(x.d, x.s, y.d, y.s, o.d, o.s);
+        }
+    }
+    // +1 if y == x, -1 if y == -x (w only, ternary only), else 0
+    __device__ __forceinline__ static int rel(TV<T> x, TV<T> y, int X)
+    {
+        if (eqv(x, y)) return 1;
+        if constexpr (!Z2)
+            if (X == 2 && tern_neg_eq(y.d, y.s, x.d, x.s)) return -1;
+        return 0;
+    }
+
+    // Sec. 3.6: first non-zero of u, then of v, made positive; w absorbs.
+    __device__ void normalise(int k)
+    {
+        if constexpr (Z2) return;
+        TV<T> u = ld(k, 0), v = ld(k, 1), w = ld(k, 2);
+        bool ch = false;
+        T lu = u.d & (~u.d + 1);
+        if (u.s & lu) {
+            u.s ^= u.d;
+            w.s ^= w.d;
+            ch = true;
+        }
+        T lv = v.d & (~v.d + 1);
+        if (v.s & lv) {
+            v.s ^= v.d;
+            w.s ^= w.d;
+            ch = true;
+        }
+        if (ch) {
+            st(k, 0, u);
+            st(k, 1, v);
+            st(k, 2, w);
+        }
+        wave_lds_sync();
+    }
+
+    __device__ __forceinline__ bool has_zero(int k) const
+    {
+        return ld(k, 0).d == 0 || ld(k, 1).d == 0 || ld(k, 2).d == 0;
+    }
+
+    // swap-remove slot h (the last term moves into it); tracked indices follow
+    __device__ void swap_remove(int h, int &tr0, int &tr1)
+    {
+        const int last = r - 1;
+        if (tr0 == h) tr0 = -1;
+        if (tr1 == h) tr1 = -1;
+        if (h != last) {
+            if (gl < 6) lds[h * 6 + gl] = lds[last * 6 + gl];
+            if (tr0 == last) tr0 = h;
+            if (tr1 == last) tr1 = h;
+        }
+        wave_lds_sync();
+        r = last;
+    }
+
+    // Candidate partners of (i, X): lane-parallel over the terms, one
+    // ballot per slot and role.  m0/m1: role 0/1 masks (bit = lane of slot q).
+    __device__ void candidates(int i, int X, uint64_t (&m0)[S], uint64_t (&m1)[S], int &n0,
+                               int &n1) const
+    {
+        const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
+        const TV<T> xi = ld(i, X), Ai = ld(i, A), Bi = ld(i, B);
+        n0 = n1 = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            bool v0 = false, v1 = false;
+            if (q * G < r) {
+                const int k = q * G + gl;
+                if (k < r && k != i) {
+                    const int sg = rel(xi, ld(k, X), X);
+                    if (sg != 0) {
+                        const TV<T> Ak = ld(k, A), Bk = ld(k, B);
+                        TV<T> o1, o2;
+                        const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
+                        const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
+                        v0 = a1 && b1;
+                        v1 = a2 && b2;
+                    }
+                }
+            }
+            m0[q] = gballot(v0);
+            m1[q] = gballot(v1);
+            n0 += popc64(m0[q]);
+            n1 += popc64(m1[q]);
+        }
+    }
+
+    __device__ __forceinline__ int select(const uint64_t (&m)[S], int c) const
+    {
+        int j = -1;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int pc = popc64(m[q]);
+            if (j < 0) {
+                if (c < pc)
+                    j = q * G + kth_bit(m[q], c);
+                else
+                    c -= pc;
+            }
+        }
+        return j;
+    }
+
+    // Flip (Sec. 3.3.1): x_j = sigma x_i; y_i += sigma y_j; z_j -= z_i;
+    // (Y,Z) = the other kinds in U<V<W order, swapped for role 1.
+    __device__ void apply_flip(int i, int j, int X, int role)
+    {
+        const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
+        const int Y = role ? B : A, Z = role ? A : B;
+        const int sg = rel(ld(i, X), ld(j, X), X);
+        TV<T> ny, nz;
+        axpy(sg, ld(i, Y), ld(j, Y), ny);
+        axpy(-1, ld(j, Z), ld(i, Z), nz);
+        st(i, Y, ny);
+        st(j, Z, nz);
+        wave_lds_sync();
+        normalise(i);
+        normalise(j);
+    }
+
+    __device__ bool try_flip(int &fi, int &fj)
+    {
+        if (r < 2) return false;
+        uint64_t m0[S], m1[S];
+        int n0, n1;
+        for (int att = 0; att < a->flip_tries; ++att) {
+            const Philox4 w = walk_block(seed, t, (uint32_t)att, 0);
+            cnt[C_ATTEMPTS]++;
+            const int i = (int)below(w.x[0], (uint32_t)r);
+            const int X = (int)below(w.x[1], 3u);
+            candidates(i, X, m0, m1, n0, n1);
+            const int n = n0 + n1;
+            if (n > 0) {
+                int c = (int)below(w.x[2], (uint32_t)n);
+                const int role = c >= n0;
+                if (role) c -= n0;
+                const int j = role ? select(m1, c) : select(m0, c);
+                apply_flip(i, j, X, role);
+                fi = i;
+                fj = j;
+                return true;
+            }
+        }
+        // exhaustive fallback over (i, X, role, j)
+        cnt[C_FALLBACKS]++;
+        uint32_t total = 0;
+        for (int i = 0; i < r; ++i)
+            for (int X = 0; X < 3; ++X) {
+                candidates(i, X, m0, m1, n0, n1);
+                total += (uint32_t)(n0 + n1);
+            }
+        if (total == 0) return false;
+        const Philox4 w = walk_block(seed, t, (uint32_t)a->flip_tries, 0);
+        uint32_t pick = below(w.x[0], total);
+        for (int i = 0; i < r; ++i)
+            for (int X = 0; X < 3; ++X) {
+                candidates(i, X, m0, m1, n0, n1);
+                if (pick < (uint32_t)n0) {
+                    const int j = select(m0, (int)pick);
+                    apply_flip(i, j, X, 0);
+                    fi = i;
+                    fj = j;
+                    return true;
+                }
+                pick -= (uint32_t)n0;
+                if (pick < (uint32_t)n1) {
+                    const int j = select(m1, (int)pick);
+                    apply_flip(i, j, X, 1);
+                    fi = i;
+                    fj = j;
+                    return true;
+                }
+                pick -= (uint32_t)n1;
+            }
+        return false;  // not reached: total counted every candidate
+    }
+
+    // Reduction (Sec. 3.3.1) between terms t and k: shared (u,v) merges w,
+    // shared (u, +-w) merges v, shared (v, +-w) merges u; returns the kind
+    // merged or -1 when no merge keeps the coefficients in the set.
+    __device__ __forceinline__ static int merge_kind(const TV<T> (&tt)[3], const TV<T> (&tk)[3],
+                                                     TV<T> &o)
+    {
+        const bool eu = eqv(tt[0], tk[0]), ev = eqv(tt[1], tk[1]);
+        const int sw = rel(tt[2], tk[2], 2);
+        if (eu && ev && axpy(1, tt[2], tk[2], o)) return 2;
+        if (eu && sw != 0 && axpy(sw, tt[1], tk[1], o)) return 1;
+        if (ev && sw != 0 && axpy(sw, tt[0], tk[0], o)) return 0;
+        return -1;
+    }
+
+    // reduce the terms modified by the flip, cascading; returns merges
+    __device__ int reduce(int &tr0, int &tr1)
+    {
+        int merges = 0;
+        for (int qq = 0; qq < 2; ++qq) {
+            for (;;) {
+                const int tt_i = qq == 0 ? tr0 : tr1;
+                if (tt_i < 0) break;
+                TV<T> tt[3] = {ld(tt_i, 0), ld(tt_i, 1), ld(tt_i, 2)};
+                int k = -1;
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    bool ok = false;
+                    if (q * G < r) {
+                        const int kk = q * G + gl;
+                        if (kk < r && kk != tt_i) {
+                            TV<T> tk[3] = {ld(kk, 0), ld(kk, 1), ld(kk, 2)};
+                            TV<T> o;
+                            ok = merge_kind(tt, tk, o) >= 0;
+                        }
+                    }
+                    const uint64_t mk = gballot(ok);
+                    if (k < 0 && mk) k = q * G + __builtin_ctzll(mk);
+                }
+                if (k < 0) break;
+                ++merges;
+                TV<T> tk[3] = {ld(k, 0), ld(k, 1), ld(k, 2)};
+                TV<T> md;
+                const int kind = merge_kind(tt, tk, md);
+                const int lo = tt_i < k ? tt_i : k, hi = tt_i < k ? k : tt_i;
+                // the partner is consumed
+                if (qq == 0 && tr1 == k) tr1 = -1;
+                if (qq == 1 && tr0 == k) tr0 = -1;
+                if (md.d == 0) {
+                    if (qq == 0) tr0 = -1; else tr1 = -1;
+                    swap_remove(hi, tr0, tr1);
+                    swap_remove(lo, tr0, tr1);
+                    break;
+                }
+                if (lo != tt_i) {
+                    st(lo, 0, tt[0]);
+                    st(lo, 1, tt[1]);
+                    st(lo, 2, tt[2]);
+                }
+                st(lo, kind, md);
+                wave_lds_sync();
+                normalise(lo);
+                if (qq == 0) tr0 = lo; else tr1 = lo;
+                swap_remove(hi, tr0, tr1);
+            }
+        }
+        return merges;
+    }
+
+    // expand (plus or split, Sec. 3.3.1), up to eight random attempts
+    __device__ bool expand()
+    {
+        if (r >= r_cap || r < 2) return false;
+        for (int att = 0; att < 8; ++att) {
+            const Philox4 w = walk_block(seed, t, (uint32_t)att, 2);
+            const int i = (int)below(w.x[0], (uint32_t)r);
+            int j = (int)below(w.x[1], (uint32_t)(r - 1));
+            if (j >= i) ++j;
+            const int perm = (int)below(w.x[2], 6u);
+            const int X = kPerm[perm][0], Y = kPerm[perm][1], Z = kPerm[perm][2];
+            const TV<T> xi = ld(i, X), yi = ld(i, Y), zi = ld(i, Z);
+            const TV<T> xj = ld(j, X), yj = ld(j, Y), zj = ld(j, Z);
+            const int nw = r;
+            if ((w.x[3] >> 31) == 0) {
+                // plus: x_i(x)(y_i+y_j)(x)z_i + x_i(x)y_j(x)(z_j-z_i) + (x_j-x_i)(x)y_j(x)z_j
+                if (eqv(xi, xj) || eqv(yi, yj) || eqv(zi, zj)) continue;
+                TV<T> sa, sb, sc;
+                if (!axpy(1, yi, yj, sa) || sa.d == 0) continue;
+                if (!axpy(-1, zj, zi, sb)) continue;
+                if (!axpy(-1, xj, xi, sc)) continue;
+                st(nw, X, sc);
+                st(nw, Y, yj);
+                st(nw, Z, zj);
+                st(j, X, xi);
+                st(j, Z, sb);
+                st(i, Y, sa);
+            } else {
+                // split: x_j(x)y_i(x)z_i + x_j(x)y_j(x)z_j + (x_i-x_j)(x)y_i(x)z_i
+                if (eqv(xi, xj)) continue;
+                TV<T> sc;
+                if (!axpy(-1, xi, xj, sc)) continue;
+                st(nw, X, sc);
+                st(nw, Y, yi);
+                st(nw, Z, zi);
+                st(i, X, xj);
+            }
+            wave_lds_sync();
+            r = nw + 1;
+            normalise(i);
+            normalise(j);
+            normalise(nw);
+            cnt[C_EXPANDS]++;
+            return true;
+        }
+        cnt[C_EXPAND_FAILS]++;
+        return false;
+    }
+
+    __device__ void copy_best()
+    {
+        uint64_t *dst = a->best + (size_t)walk * a->cap * 6;
+        for (int k = gl; k < r; k += G)
+#pragma unroll
+            for (int x = 0; x < 6; ++x) dst[k * 6 + x] = (uint64_t)lds[k * 6 + x];
+    }
+
+    __device__ void restart_check()
+    {
+        if (a->plateau > 0 && t - plateau_start >= a->plateau) {
+            const bool from_best = a->restart_from_best != 0;
+            const uint64_t *src = (from_best ? (const uint64_t *)a->best : a->start) +
+                                  (size_t)walk * a->cap * 6;
+            const int rr = from_best ? best_rank : start_rank;
+            for (int k = gl; k < rr; k += G)
+#pragma unroll
+                for (int x = 0; x < 6; ++x) lds[k * 6 + x] = (T)src[k * 6 + x];
+            wave_lds_sync();
+            r = rr;
+            plateau_start = t;
+            cnt[C_RESTARTS]++;
+        }
+    }
+
+    __device__ void iteration()
+    {
+        cnt[C_ITERS]++;
+        int fi = -1, fj = -1;
+        if (!try_flip(fi, fj)) {
+            // Algorithm 1: no flip -> expand, continue
+            cnt[C_DEAD_ENDS]++;
+            expand();
+            restart_check();
+            return;
+        }
+        cnt[C_FLIPS]++;
+        int tr0 = fi, tr1 = fj;
+        const bool zi = has_zero(fi), zj = has_zero(fj);
+        if (zi && zj) {
+            swap_remove(fi > fj ? fi : fj, tr0, tr1);
+            swap_remove(fi > fj ? fj : fi, tr0, tr1);
+            cnt[C_ZERO_REMOVED] += 2;
+        } else if (zi) {
+            swap_remove(fi, tr0, tr1);
+            cnt[C_ZERO_REMOVED]++;
+        } else if (zj) {
+            swap_remove(fj, tr0, tr1);
+            cnt[C_ZERO_REMOVED]++;
+        }
+        // gates: block (t, 0, 1), drawn only when one of them can matter
+        uint32_t g0 = 0, g1 = 0, g2 = 0;
+        const bool need = (r == best_rank && a->t_eq > 0) || a->t_reduce <= 0xFFFFFFFFull ||
+                          a->t_expand > 0;
+        if (need) {
+            const Philox4 g = walk_block(seed, t, 0u, 1u);
+            g0 = g.x[0];
+            g1 = g.x[1];
+            g2 = g.x[2];
+        }
+        if (r < best_rank) {
+            copy_best();
+            best_rank = r;
+            plateau_start = t;
+            if (gl == 0 && n_rec < a->rec_cap) {
+                tsf_record *rc = a->rec + (size_t)walk * a->rec_cap + n_rec;
+                rc->iter = t;
+                rc->rank = r;
+                rc->reserved = 0;
+            }
+            n_rec++;
+            cnt[C_IMPROVEMENTS]++;
+        } else if (r == best_rank && (uint64_t)g0 < a->t_eq) {
+            copy_best();
+            cnt[C_EQ_ACCEPTS]++;
+        }
+        if ((uint64_t)g1 < a->t_reduce) cnt[C_MERGES] += (uint32_t)reduce(tr0, tr1);
+        if ((uint64_t)g2 < a->t_expand && r <= best_rank + 2 && r < r_cap) expand();
+        restart_check();
+    }
+};
+
+__device__ __forceinline__ int flen(int m, int n, int p, int X)
+{
+    return X == 0 ? m * n : X == 1 ? n * p : p * m;
+}
+
+template <int G, int S, typename T, bool Z2>
+__global__ void __launch_bounds__(256) walk_kernel(KArgs a)
+{
+    extern __shared__ uint64_t smem_u64[];
+    T *smem = reinterpret_cast<T *>(smem_u64);
+    constexpr int W = 64 / G;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / G;
+    const int wpb = blockDim.x >> 6;
+    const int64_t walk = ((int64_t)blockIdx.x * wpb + wave) * W + grp;
+    if (walk >= a.n_walks) return;  // the whole group leaves together
+
+    Walker<G, S, T, Z2> wk;
+    wk.gl = lane % G;
+    wk.gshift = grp * G;
+    wk.lds = smem + (size_t)(wave * W + grp) * a.cap * 6;
+    wk.a = &a;
+    wk.walk = walk;
+    tsf_walk_header *h = a.hdr + walk;
+    const int m = h->m, n = h->n, p = h->p;
+    int done = h->done;
+    // a header that does not fit this kernel is never advanced
+    const int lmax = max(flen(m, n, p, 0), max(flen(m, n, p, 1), flen(m, n, p, 2)));
+    const bool sane = m >= 1 && n >= 1 && p >= 1 && lmax <= a.max_len &&
+                      lmax <= (int)(8 * sizeof(T)) && h->mode == (Z2 ? 1 : 0) &&
+                      h->r_cap <= a.cap && h->rank >= 0 && h->rank <= h->r_cap &&
+                      h->best_rank >= 0 && h->best_rank <= a.cap && h->start_rank >= 0 &&
+                      h->start_rank <= a.cap;
+    if (!sane || done != 0) {
+        if (!sane && wk.gl == 0 && done == 0) h->done = -1;
+        return;
+    }
+    wk.seed = a.base_seed + (uint64_t)(a.first_walk_id + walk);
+    wk.r = h->rank;
+    wk.r_cap = h->r_cap;
+    wk.best_rank = h->best_rank;
+    wk.start_rank = h->start_rank;
+    wk.target = h->target_rank;
+    wk.n_rec = h->n_rec;
+    wk.t = h->t;
+    wk.plateau_start = h->plateau_start;
+#pragma unroll
+    for (int c = 0; c < C_NUM; ++c) wk.cnt[c] = 0;
+
+    const uint64_t *src = a.cur + (size_t)walk * a.cap * 6;
+    for (int k = wk.gl; k < wk.r; k += G)
+#pragma unroll
+        for (int x = 0; x < 6; ++x) wk.lds[k * 6 + x] = (T)src[k * 6 + x];
+    wave_lds_sync();
+
+    for (int64_t it = 0; it < a.n_iters; ++it) {
+        if (wk.best_rank <= wk.target) done = 1;
+        if (done || wk.t >= a.max_iters) break;
+        wk.t += 1;
+        wk.iteration();
+    }
+    if (wk.best_rank <= wk.target) done = 1;
+
+    uint64_t *dst = a.cur + (size_t)walk * a.cap * 6;
+    for (int k = wk.gl; k < wk.r; k += G)
+#pragma unroll
+        for (int x = 0; x < 6; ++x) dst[k * 6 + x] = (uint64_t)wk.lds[k * 6 + x];
+    if (wk.gl == 0) {
+        h->rank = wk.r;
+        h->best_rank = wk.best_rank;
+        h->done = done;
+        h->n_rec = wk.n_rec;
+        h->t = wk.t;
+        h->plateau_start = wk.plateau_start;
+        for (int c = 0; c < C_NUM; ++c) h->counters[c] += wk.cnt[c];
+    }
+}
+
+using KernelFn = void (*)(KArgs);
+
+}  // namespace tsfk

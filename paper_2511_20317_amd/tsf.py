@@ -1,0 +1,338 @@
+"""ctypes binding of libtsf (include/tsf.h): argument marshalling only.
+
+Every step of the walk runs in libtsf's HIP kernels; torch is used for device
+memory and streams.  If libtsf.so is missing the import fails loudly: there is
+no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsf.so")
+
+TSF_TERNARY = 0
+TSF_Z2 = 1
+ALWAYS = 1 << 32                # Bernoulli threshold of probability 1
+EQ_ACCEPT = 42949673            # round(0.01 * 2^32): Algorithm 1's 1% equal-rank acceptance
+
+STATUS = {0: "TSF_OK", -1: "TSF_E_ARG", -2: "TSF_E_FORMAT", -3: "TSF_E_CAPACITY",
+          -4: "TSF_E_NOT_TERNARY", -5: "TSF_E_INVALID_SCHEME", -6: "TSF_E_DEVICE",
+          -7: "TSF_E_STATE"}
+
+COUNTER_NAMES = ("iters", "flips", "attempts", "fallbacks", "dead_ends", "zero_removed",
+                 "merges", "expands", "expand_fails", "restarts", "eq_accepts",
+                 "improvements")
+
+
+class TsfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Dims(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("p", C.c_int32), ("rank", C.c_int32),
+                ("capacity", C.c_int32), ("mode", C.c_int32)]
+
+
+class CScheme(C.Structure):
+    _fields_ = [("d", Dims), ("U", C.POINTER(C.c_int8)), ("V", C.POINTER(C.c_int8)),
+                ("W", C.POINTER(C.c_int8))]
+
+
+class WalkParams(C.Structure):
+    _fields_ = [("base_seed", C.c_uint64), ("first_walk_id", C.c_int64),
+                ("max_iters", C.c_int64), ("plateau", C.c_int64), ("flip_tries", C.c_int32),
+                ("restart_from_best", C.c_int32), ("t_eq", C.c_uint64),
+                ("t_reduce", C.c_uint64), ("t_expand", C.c_uint64)]
+
+
+class WalkBatchC(C.Structure):
+    _fields_ = [("n_walks", C.c_int32), ("capacity", C.c_int32), ("rec_cap", C.c_int32),
+                ("mode", C.c_int32), ("max_len", C.c_int32), ("reserved", C.c_int32),
+                ("hdr", C.c_void_p), ("cur", C.c_void_p), ("best", C.c_void_p),
+                ("start", C.c_void_p), ("rec", C.c_void_p)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("lanes_per_walk", C.c_int32), ("waves_per_block", C.c_int32)]
+
+
+# numpy view of tsf_walk_header (160 bytes)
+HEADER_DTYPE = np.dtype([("m", "<i4"), ("n", "<i4"), ("p", "<i4"), ("mode", "<i4"),
+                         ("r_cap", "<i4"), ("target_rank", "<i4"), ("rank", "<i4"),
+                         ("best_rank", "<i4"), ("start_rank", "<i4"), ("done", "<i4"),
+                         ("n_rec", "<i4"), ("reserved", "<i4"), ("t", "<i8"),
+                         ("plateau_start", "<i8"), ("counters", "<i8", (12,))])
+assert HEADER_DTYPE.itemsize == 160
+RECORD_DTYPE = np.dtype([("iter", "<i8"), ("rank", "<i4"), ("reserved", "<i4")])
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libtsf.so is not built (run paper_2511_20317_amd/build.py); "
+                              "there is no fallback implementation")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.tsf_last_error.restype = C.c_char_p
+        for name, args in [
+            ("tsf_init_scheme", [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(CScheme)]),
+            ("tsf_verify", [P(CScheme), P(C.c_int64)]),
+            ("tsf_normalise", [P(CScheme)]),
+            ("tsf_reduce", [P(CScheme), P(C.c_int32)]),
+            ("tsf_meta_project", [P(CScheme), C.c_int32, C.c_int32, P(CScheme)]),
+            ("tsf_meta_extend", [P(CScheme), C.c_int32, P(CScheme)]),
+            ("tsf_pack", [P(CScheme), C.c_void_p]),
+            ("tsf_unpack", [C.c_void_p, P(Dims), P(CScheme)]),
+            ("tsf_ctx_create", [P(C.c_void_p)]),
+            ("tsf_ctx_destroy", [C.c_void_p]),
+            ("tsf_walk_init", [C.c_void_p, P(WalkBatchC), C.c_void_p]),
+            ("tsf_walk", [C.c_void_p, P(WalkParams), P(WalkBatchC), C.c_int64, P(Launch),
+                          C.c_void_p]),
+            ("tsf_verify_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p]),
+        ]:
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != 0:
+        raise TsfError(status, lib().tsf_last_error().decode())
+    return status
+
+
+# ---------------------------------------------------------------------------
+# host schemes
+# ---------------------------------------------------------------------------
+class Scheme:
+    """A scheme (m,n,p:r) in the int8 interchange form of tsf.h."""
+
+    def __init__(self, m, n, p, U, V, W, mode=TSF_TERNARY, capacity=None):
+        self.m, self.n, self.p, self.mode = int(m), int(n), int(p), int(mode)
+        r = int(np.asarray(U).shape[0])
+        self.capacity = max(int(capacity or r), r, 1)
+        lu, lv, lw = m * n, n * p, p * m
+        self.U = np.zeros((self.capacity, lu), np.int8)
+        self.V = np.zeros((self.capacity, lv), np.int8)
+        self.W = np.zeros((self.capacity, lw), np.int8)
+        self.U[:r] = U
+        self.V[:r] = V
+        self.W[:r] = W
+        self.rank = r
+
+    @classmethod
+    def empty(cls, m, n, p, capacity, mode=TSF_TERNARY):
+        s = cls(m, n, p, np.zeros((0, m * n)), np.zeros((0, n * p)), np.zeros((0, p * m)),
+                mode, capacity)
+        return s
+
+    def c(self):
+        cs = CScheme()
+        cs.d = Dims(self.m, self.n, self.p, self.rank, self.capacity, self.mode)
+        cs.U = self.U.ctypes.data_as(C.POINTER(C.c_int8))
+        cs.V = self.V.ctypes.data_as(C.POINTER(C.c_int8))
+        cs.W = self.W.ctypes.data_as(C.POINTER(C.c_int8))
+        return cs
+
+    def _take(self, cs):
+        self.m, self.n, self.p = cs.d.m, cs.d.n, cs.d.p
+        self.rank, self.mode = cs.d.rank, cs.d.mode
+
+    def live(self):
+        """(U, V, W) of the live terms"""
+        r = self.rank
+        return self.U[:r].copy(), self.V[:r].copy(), self.W[:r].copy()
+
+    def copy(self):
+        return Scheme(self.m, self.n, self.p, *self.live(), self.mode, self.capacity)
+
+
+def init_scheme(m, n, p, mode=TSF_TERNARY, capacity=None):
+    s = Scheme.empty(m, n, p, capacity or m * n * p, mode)
+    cs = s.c()
+    check(lib().tsf_init_scheme(m, n, p, mode, C.byref(cs)))
+    s._take(cs)
+    return s
+
+
+def verify(s: Scheme) -> int:
+    out = C.c_int64()
+    check(lib().tsf_verify(C.byref(s.c()), C.byref(out)))
+    return int(out.value)
+
+
+def normalise(s: Scheme) -> Scheme:
+    cs = s.c()
+    check(lib().tsf_normalise(C.byref(cs)))
+    s._take(cs)
+    return s
+
+
+def reduce(s: Scheme) -> int:
+    cs = s.c()
+    n = C.c_int32()
+    check(lib().tsf_reduce(C.byref(cs), C.byref(n)))
+    s._take(cs)
+    return int(n.value)
+
+
+def meta_project(s: Scheme, axis: int, index: int, capacity=None) -> Scheme:
+    out = Scheme.empty(1, 1, 1, 1)
+    dims = [s.m, s.n, s.p]
+    dims[axis] -= 1 if dims[axis] > 1 else 0
+    out = Scheme.empty(*dims, capacity or s.capacity, s.mode)
+    cs = out.c()
+    check(lib().tsf_meta_project(C.byref(s.c()), axis, index, C.byref(cs)))
+    out._take(cs)
+    return out
+
+
+def meta_extend(s: Scheme, axis: int, capacity=None) -> Scheme:
+    dims = [s.m, s.n, s.p]
+    dims[axis] += 1
+    extra = [s.n * s.p, s.m * s.p, s.m * s.n][axis]
+    out = Scheme.empty(*dims, capacity or (s.rank + extra), s.mode)
+    cs = out.c()
+    check(lib().tsf_meta_extend(C.byref(s.c()), axis, C.byref(cs)))
+    out._take(cs)
+    return out
+
+
+def pack(s: Scheme, capacity=None) -> np.ndarray:
+    """-> uint64 array (capacity, 6) in the one-bit form"""
+    cap = capacity or s.capacity
+    if cap < s.rank:
+        raise ValueError("capacity below rank")
+    tmp = Scheme(s.m, s.n, s.p, *s.live(), s.mode, cap)
+    out = np.zeros((cap, 6), np.uint64)
+    check(lib().tsf_pack(C.byref(tmp.c()), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def unpack(packed, m, n, p, rank, mode=TSF_TERNARY) -> Scheme:
+    packed = np.ascontiguousarray(packed, dtype=np.uint64).reshape(-1, 6)
+    cap = max(packed.shape[0], 1)
+    out = Scheme.empty(m, n, p, cap, mode)
+    d = Dims(m, n, p, rank, cap, mode)
+    cs = out.c()
+    check(lib().tsf_unpack(packed.ctypes.data_as(C.c_void_p), C.byref(d), C.byref(cs)))
+    out._take(cs)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# walks on the GPU
+# ---------------------------------------------------------------------------
+def walk_params(base_seed=0, first_walk_id=0, max_iters=100000, plateau=20000, flip_tries=8,
+                restart_from_best=0, t_eq=EQ_ACCEPT, t_reduce=ALWAYS, t_expand=0):
+    return WalkParams(base_seed, first_walk_id, max_iters, plateau, flip_tries,
+                      restart_from_best, t_eq, t_reduce, t_expand)
+
+
+class Context:
+    def __init__(self):
+        self.ptr = C.c_void_p()
+        check(lib().tsf_ctx_create(C.byref(self.ptr)))
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.tsf_ctx_destroy(self.ptr)
+            self.ptr = None
+
+
+class WalkBatch:
+    """Device buffers of a batch of walks (torch tensors as plain memory).
+
+    groups: list of (start_scheme, n_walks, r_cap, target_rank); walks are laid
+    out group after group.  All groups share one mode.
+    """
+
+    def __init__(self, groups, capacity=None, rec_cap=64, device="cuda"):
+        import torch
+        self.torch = torch
+        modes = {g[0].mode for g in groups}
+        if len(modes) != 1:
+            raise ValueError("one mode per batch")
+        self.mode = modes.pop()
+        self.n_walks = int(sum(g[1] for g in groups))
+        self.capacity = int(capacity or max(g[2] for g in groups))
+        self.rec_cap = int(rec_cap)
+        self.max_len = max(max(s.m * s.n, s.n * s.p, s.p * s.m) for s, _, _, _ in groups)
+        hdr = np.zeros(self.n_walks, HEADER_DTYPE)
+        start = np.zeros((self.n_walks, self.capacity, 6), np.uint64)
+        w = 0
+        self.groups = []
+        for s, nw, r_cap, target in groups:
+            if r_cap > self.capacity or s.rank > r_cap:
+                raise ValueError("need start rank <= r_cap <= capacity")
+            ns = normalise(s.copy())
+            packed = pack(ns, self.capacity)
+            hdr["m"][w:w + nw], hdr["n"][w:w + nw], hdr["p"][w:w + nw] = s.m, s.n, s.p
+            hdr["mode"][w:w + nw] = s.mode
+            hdr["r_cap"][w:w + nw] = r_cap
+            hdr["target_rank"][w:w + nw] = target
+            hdr["start_rank"][w:w + nw] = s.rank
+            start[w:w + nw] = packed
+            self.groups.append((w, nw, (s.m, s.n, s.p), r_cap, target))
+            w += nw
+        dev = torch.device(device)
+        self.hdr = torch.from_numpy(hdr.view(np.uint8).copy()).to(dev)
+        self.start = torch.from_numpy(start.view(np.int64)).to(dev)
+        self.cur = torch.zeros_like(self.start)
+        self.best = torch.zeros_like(self.start)
+        self.rec = torch.zeros((self.n_walks, max(self.rec_cap, 1), 2), dtype=torch.int64,
+                               device=dev)
+
+    def c(self):
+        return WalkBatchC(self.n_walks, self.capacity, self.rec_cap, self.mode, self.max_len, 0,
+                          self.hdr.data_ptr(), self.cur.data_ptr(), self.best.data_ptr(),
+                          self.start.data_ptr(), self.rec.data_ptr())
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def init(self, ctx: Context):
+        check(lib().tsf_walk_init(ctx.ptr, C.byref(self.c()), self._stream()))
+
+    def walk(self, ctx: Context, prm: WalkParams, n_iters: int, lanes_per_walk=0,
+             waves_per_block=0):
+        la = Launch(lanes_per_walk, waves_per_block)
+        check(lib().tsf_walk(ctx.ptr, C.byref(prm), C.byref(self.c()), int(n_iters),
+                             C.byref(la), self._stream()))
+
+    def verify_device(self, which=1):
+        """Brent check of cur (0), best (1) or start (2) of every walk on the GPU."""
+        out = self.torch.empty(self.n_walks, dtype=self.torch.int64, device=self.hdr.device)
+        check(lib().tsf_verify_batch(C.byref(self.c()), which, C.c_void_p(out.data_ptr()),
+                                     self._stream()))
+        return out
+
+    # ------------------------------------------------------------ read back
+    def headers(self):
+        return self.hdr.cpu().numpy().view(HEADER_DTYPE).copy()
+
+    def records(self, walk):
+        h = self.headers()[walk]
+        n = min(int(h["n_rec"]), self.rec_cap)
+        rec = self.rec[walk, :n].cpu().numpy()
+        return [(int(a), int(b & 0xFFFFFFFF)) for a, b in rec]
+
+    def scheme(self, walk, which="best", headers=None):
+        h = (headers if headers is not None else self.headers())[walk]
+        buf = {"cur": self.cur, "best": self.best, "start": self.start}[which]
+        rank = {"cur": h["rank"], "best": h["best_rank"], "start": h["start_rank"]}[which]
+        packed = buf[walk].cpu().numpy().view(np.uint64)
+        return unpack(packed, int(h["m"]), int(h["n"]), int(h["p"]), int(rank), int(h["mode"]))
+
+    def counters(self, walk, headers=None):
+        h = (headers if headers is not None else self.headers())[walk]
+        return {name: int(h["counters"][k]) for k, name in enumerate(COUNTER_NAMES)}

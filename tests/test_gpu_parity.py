@@ -1,0 +1,131 @@
+"""GPU walks (libtsf HIP kernels) against the CPU oracle, bit for bit: current
+and best schemes, counters, records and headers of every compared walk."""
+import numpy as np
+import pytest
+
+from paper_2511_20317_amd import tsf
+from tests.gpu_parity import compare, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return tsf.Context()
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _std(m, n, p, mode=tsf.TSF_TERNARY):
+    return tsf.init_scheme(m, n, p, mode)
+
+
+def _run(ctx, groups, prm, n_iters, splits=None, lanes=0, wpb=0, rec_cap=64, capacity=None):
+    b = tsf.WalkBatch(groups, capacity=capacity, rec_cap=rec_cap)
+    b.init(ctx)
+    for chunk in (splits or [n_iters]):
+        b.walk(ctx, prm, chunk, lanes, wpb)
+    _sync()
+    return b
+
+
+def test_config1_2x2x2_all_walks(ctx):
+    """(2,2,2) ternary: 256 walks from the standard rank-8 scheme, seed 0,
+    <= 1e5 iterations, plateau 2e4, target 7 -- every walk against the oracle."""
+    groups = [(_std(2, 2, 2), 256, 16, 7)]
+    prm = tsf.walk_params(base_seed=0, max_iters=100000, plateau=20000)
+    b = _run(ctx, groups, prm, 100000)
+    compare(b, run_oracle(groups, prm, range(256), 100000), "cfg1")
+    hdr = b.headers()
+    assert (hdr["best_rank"] == 7).all() and (hdr["done"] == 1).all()
+    nv = b.verify_device(which=1).cpu().numpy()
+    assert (nv == 0).all()
+
+
+@pytest.mark.parametrize("lanes,wpb", [(8, 4), (16, 2), (32, 1), (64, 4)])
+def test_lanes_per_walk_and_round_split_invariance(ctx, lanes, wpb):
+    groups = [(_std(3, 3, 3), 48, 35, 23)]
+    prm = tsf.walk_params(base_seed=7, max_iters=3000, plateau=1000, t_expand=1 << 28)
+    splits = [1, 999, 1500, 500]
+    b = _run(ctx, groups, prm, 3000, splits=splits, lanes=lanes, wpb=wpb)
+    compare(b, run_oracle(groups, prm, range(48), 3000), "333 G=%d" % lanes)
+
+
+def test_3x3x3_restarts_expand_partial_reduce(ctx):
+    groups = [(_std(3, 3, 3), 32, 35, 23)]
+    prm = tsf.walk_params(base_seed=11, max_iters=20000, plateau=3000, t_expand=1 << 28,
+                          t_reduce=1 << 31, restart_from_best=0)
+    b = _run(ctx, groups, prm, 20000)
+    compare(b, run_oracle(groups, prm, range(32), 20000), "333 mix")
+    prm2 = tsf.walk_params(base_seed=12, max_iters=8000, plateau=2000, restart_from_best=1,
+                           t_expand=1 << 27)
+    b = _run(ctx, groups, prm2, 8000, splits=[3000, 5000])
+    compare(b, run_oracle(groups, prm2, range(32), 8000), "333 restart-best")
+
+
+def test_mixed_formats_one_launch(ctx):
+    fmts = [(3, 3, 4), (3, 4, 5), (4, 4, 4), (4, 4, 5)]
+    groups = [(_std(*f), 12, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
+    prm = tsf.walk_params(base_seed=3, max_iters=2000, plateau=800, t_expand=1 << 27)
+    for lanes in (8, 32):
+        b = _run(ctx, groups, prm, 2000, lanes=lanes)
+        compare(b, run_oracle(groups, prm, range(48), 2000), "mixed G=%d" % lanes)
+
+
+def test_z2_mode(ctx):
+    groups = [(_std(2, 2, 2, tsf.TSF_Z2), 32, 16, 7), (_std(3, 3, 4, tsf.TSF_Z2), 16, 44, 0)]
+    prm = tsf.walk_params(base_seed=5, max_iters=6000, plateau=2000, t_expand=1 << 27)
+    b = _run(ctx, groups, prm, 6000)
+    compare(b, run_oracle(groups, prm, range(48), 6000), "z2")
+    assert (b.verify_device(which=0).cpu().numpy() == 0).all()
+
+
+def test_large_formats_64bit_masks(ctx):
+    groups = [(_std(4, 5, 12), 3, 248, 0), (_std(6, 7, 9), 2, 386, 0)]
+    prm = tsf.walk_params(base_seed=9, max_iters=300, plateau=200, t_expand=1 << 28)
+    b = _run(ctx, groups, prm, 300, lanes=64, wpb=1)
+    compare(b, run_oracle(groups, prm, range(5), 300), "large")
+    assert (b.verify_device(which=1).cpu().numpy() == 0).all()
+
+
+def test_invalid_start_and_header_are_flagged(ctx):
+    s = _std(2, 2, 2)
+    bad = s.copy()
+    bad.W[3, 0] = 1  # breaks the Brent equations, still ternary and normalised
+    groups = [(s, 2, 16, 7), (bad, 2, 16, 7)]
+    b = tsf.WalkBatch(groups, rec_cap=8)
+    b.init(ctx)
+    nv = b.verify_device(which=2).cpu().numpy()
+    assert nv[0] == 0 and nv[1] == 0 and nv[2] > 0 and nv[3] > 0
+    # a start that is not normalised is refused by the init kernel
+    import torch
+    st = b.start.cpu()
+    st[3, 0, 1] = st[3, 0, 0]  # u of term 0 becomes negative
+    b.start.copy_(st.to(b.start.device))
+    b.init(ctx)
+    prm = tsf.walk_params(max_iters=100)
+    b.walk(ctx, prm, 100)
+    _sync()
+    hdr = b.headers()
+    assert hdr["done"][3] == -2 and hdr["t"][3] == 0
+    assert hdr["t"][0] > 0
+    del torch
+
+
+def test_config2_full_batch_sampled(ctx):
+    """(3,3,3) ternary, 65,536 walks, seeds 0..65535, plateau 5e4, target 23:
+    the full batch in the launch shape the benchmark uses, sampled walks
+    checked against the oracle."""
+    groups = [(_std(3, 3, 3), 65536, 35, 23)]
+    prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
+    b = _run(ctx, groups, prm, 4000)
+    rng = np.random.default_rng(0)
+    walks = sorted(set(rng.integers(0, 65536, 24).tolist()) | {0, 65535})
+    compare(b, run_oracle(groups, prm, walks, 4000), "cfg2")
+    nv = b.verify_device(which=1).cpu().numpy()
+    assert (nv == 0).all()
