@@ -1,0 +1,181 @@
+"""Benchmark: flips/sec of the ternary flip-graph walk on one MI355X, and the
+time to reach rank 23 at (3,3,3).
+
+Workload (defaults): format (3,3,3), ternary, 65,536 walks from the standard
+rank-27 scheme, walk seeds 0..65535, at most 1e6 iterations per walk, plateau
+restart after 5e4 iterations without improvement, target rank 23, uniform
+flip proposals.  One step = one round of `--iters` iterations of every walk
+(the walk kernel) followed by the GPU Brent check of every walk's best scheme;
+the default 10 timed steps of 1e5 iterations cover the whole 1e6 budget.
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
+build measures one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x int32 lanes/clk/CU x clock = 39.3e12 op/s
+PEAK_HBM = 8.0e12
+
+
+def ops_per_iteration(cnt, iters, mean_rank, wd=1):
+    """Algorithmic 32-bit integer operations of one walk iteration, from the
+    walk's own counters (model stated in the design doc):
+      Philox block          100 ops (10 rounds x (4 mul + 4 xor + 2 add))
+      partner scan          (4*wd + 2) ops per term per attempt
+      full search           2 passes x 3 kinds x r terms x r partners x (4*wd + 2)
+      flip + normalisation  30*wd
+      reduction scan        2 modified terms x r x (7*wd + 2)
+      bookkeeping           20
+    """
+    r = mean_rank
+    a = cnt["attempts"] / iters
+    fb = cnt["fallbacks"] / iters
+    gate = 1.0
+    exp_blocks = (cnt["expands"] + 8 * cnt["expand_fails"]) / iters
+    philox = 100.0 * (a + fb + gate + exp_blocks)
+    scan = a * r * (4 * wd + 2)
+    full = fb * 2 * 3 * r * r * (4 * wd + 2)
+    apply = 30.0 * wd * cnt["flips"] / iters
+    red = 2 * r * (7 * wd + 2) * cnt["flips"] / iters
+    return philox + scan + full + apply + red + 20.0
+
+
+def cpu_baseline(n_walks=256, iters=100000, threads=None):
+    """The oracle as it stands, on the host cores: (3,3,3) walks from the
+    standard scheme with the benchmark's parameters, a bounded sample."""
+    from oracle import pyoracle as O
+    threads = threads or os.cpu_count() or 1
+    start = O.standard(3, 3, 3)
+    prm = O.make_params(seed=0, max_iters=1000000, plateau=50000, target_rank=23, r0=27)
+    t0 = time.perf_counter()
+    ws = O.run_many(start, prm, 0, 0, n_walks, iters, threads)
+    dt = time.perf_counter() - t0
+    flips = sum(w.c.flips for w in ws)
+    its = sum(w.c.iters for w in ws)
+    return {"value": flips / dt, "unit": "flips/s", "cores": threads, "kind": "oracle",
+            "sample": "%d walks x %d iterations of the (3,3,3) workload (seeds 0..%d), "
+                      "%.1f s wall, %.3g iterations/s" % (n_walks, iters, n_walks - 1, dt,
+                                                          its / dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=100000, help="iterations per walk per step")
+    ap.add_argument("--walks", type=int, default=65536)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per walk (0: library choice)")
+    ap.add_argument("--wpb", type=int, default=0, help="waves per workgroup (0: library choice)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--cpu-walks", type=int, default=256)
+    ap.add_argument("--cpu-iters", type=int, default=100000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the walks shard by walk id with no "
+              "communication, so several GPUs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2511_20317_amd import tsf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    ctx = tsf.Context()
+    target = 23
+    groups = [(tsf.init_scheme(3, 3, 3), args.walks, 35, target)]
+    prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
+    batch = tsf.WalkBatch(groups, rec_cap=32)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        batch.init(ctx)
+        batch.walk(ctx, prm, args.iters, args.lanes, args.wpb)
+        batch.verify_device(1)
+    torch.cuda.synchronize()
+
+    batch.init(ctx)
+    hdr0 = torch.cuda.synchronize() or batch.headers()
+    best_col = batch.hdr.view(torch.int32).view(args.walks, 40)[:, 7]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    ladder = {}
+    bad_total = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        batch.walk(ctx, prm, args.iters, args.lanes, args.wpb)
+        ev[k][1].record(stream)
+        nv = batch.verify_device(1)
+        bad_total += int((nv != 0).sum().item())
+        best_now = int(best_col.min().item())  # synchronises: round granularity
+        now = time.perf_counter() - t0
+        for rank in (26, 25, 24, 23):
+            if best_now <= rank and rank not in ladder:
+                ladder[rank] = now
+        print("step %d/%d: %.2f s, best rank %d" % (k + 1, args.steps, now, best_now),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    hdr = batch.headers()
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    cnt = {name: int(hdr["counters"][:, k].sum() - hdr0["counters"][:, k].sum())
+           for k, name in enumerate(tsf.COUNTER_NAMES)}
+    flips = cnt["flips"]
+    iters = max(cnt["iters"], 1)
+    value = flips / wall
+    mean_rank = float(hdr["rank"].mean())
+    per_launch_iters = iters / args.steps
+    ops_iter = ops_per_iteration(cnt, iters, (mean_rank + 27) / 2)
+    avg_ms = float(np.mean(kernel_ms))
+    achieved = ops_iter * per_launch_iters / (avg_ms * 1e-3)
+    ranks = np.bincount(hdr["best_rank"], minlength=28)
+    out = {
+        "metric": "flips/sec on 1 GPU and time-to-rank-23 at (3,3,3), learned vs uniform proposal",
+        "value": value,
+        "unit": "flips/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "(3,3,3) ternary walks from the standard rank-27 scheme, "
+                               "uniform proposals", "walks": args.walks,
+                   "iters_per_step": args.iters, "max_iters": 1000000, "plateau": 50000,
+                   "target_rank": target, "seeds": "0..%d" % (args.walks - 1),
+                   "lanes_per_walk": args.lanes or "library", "parallelism": "1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+                     "kernel": "walk_kernel", "kernel_avg_ms": avg_ms,
+                     "ops_per_iteration": ops_iter},
+        "time_to_rank_s": ladder,
+        "time_to_rank_23_s": ladder.get(23),
+        "walks_at_rank": {str(r): int(ranks[r]) for r in range(20, 28) if ranks[r]},
+        "iterations_per_s": iters / wall,
+        "attempts_per_iteration": cnt["attempts"] / iters,
+        "fallback_rate": cnt["fallbacks"] / iters,
+        "best_schemes_failing_brent": bad_total,
+        "learned_vs_uniform": None,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_walks, args.cpu_iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

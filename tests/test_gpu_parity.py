@@ -72,7 +72,7 @@ def test_mixed_formats_one_launch(ctx):
     fmts = [(3, 3, 4), (3, 4, 5), (4, 4, 4), (4, 4, 5)]
     groups = [(_std(*f), 12, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
     prm = tsf.walk_params(base_seed=3, max_iters=2000, plateau=800, t_expand=1 << 27)
-    for lanes in (8, 32):
+    for lanes in (16, 32, 64):
         b = _run(ctx, groups, prm, 2000, lanes=lanes)
         compare(b, run_oracle(groups, prm, range(48), 2000), "mixed G=%d" % lanes)
 

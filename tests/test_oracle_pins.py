@@ -30,7 +30,7 @@ def test_philox_known_answers(ctr, key, want):
 
 @pytest.mark.gpu
 def test_philox_against_rocrand_host_generator():
-    """rocRAND's host Philox4x32-10 generator: output 4k..4k+3 is the block
+    """rocRAND's blocking host Philox4x32-10 generator: output 4k..4k+3 is the block
     with counter (k,0,0,0) and key = the 64-bit seed.  Marked gpu: the
     generator initialises the HIP runtime, which aborts without a device."""
     import ctypes as C
@@ -39,7 +39,7 @@ def test_philox_against_rocrand_host_generator():
     except OSError:
         pytest.skip("rocRAND not installed")
     gen = C.c_void_p()
-    if L.rocrand_create_generator_host(C.byref(gen), 404) != 0:
+    if L.rocrand_create_generator_host_blocking(C.byref(gen), 404) != 0:
         pytest.skip("rocRAND host generator unavailable")
     try:
         seed = 0x0123456789ABCDEF
