@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--walks", type=int, default=65536)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per walk (0: library choice)")
     ap.add_argument("--wpb", type=int, default=0, help="waves per workgroup (0: library choice)")
+    ap.add_argument("--strategy", type=int, default=0,
+                    help="1 attempt-parallel, 2 term-parallel (0: library choice)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-walks", type=int, default=256)
     ap.add_argument("--cpu-iters", type=int, default=100000)
@@ -99,7 +101,7 @@ def main():
 
     for _ in range(args.warmup):
         batch.init(ctx)
-        batch.walk(ctx, prm, args.iters, args.lanes, args.wpb)
+        batch.walk(ctx, prm, args.iters, args.lanes, args.wpb, args.strategy)
         batch.verify_device(1)
     torch.cuda.synchronize()
 
@@ -114,7 +116,7 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(stream)
-        batch.walk(ctx, prm, args.iters, args.lanes, args.wpb)
+        batch.walk(ctx, prm, args.iters, args.lanes, args.wpb, args.strategy)
         ev[k][1].record(stream)
         nv = batch.verify_device(1)
         bad_total += int((nv != 0).sum().item())

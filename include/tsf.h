@@ -193,12 +193,16 @@ typedef struct {
     tsf_record *rec;
 } tsf_walk_batch;
 
-/* Launch configuration: lanes cooperating on one walk (8, 16, 32 or 64, i.e.
- * 8, 4, 2 or 1 walks per 64-lane wavefront) and wavefronts per workgroup.
- * 0 in both fields lets the library choose (its autotuned table). */
+/* Launch configuration.  strategy: 1 = attempt-parallel (each lane of a walk
+ * evaluates a different random flip attempt; capacity <= 64 only),
+ * 2 = term-parallel (the lanes of a walk split its terms; any capacity).
+ * lanes_per_walk: 8, 16, 32 or 64 (8, 4, 2 or 1 walks per 64-lane
+ * wavefront; at most 32 for attempt-parallel).  waves_per_block: 1..4.
+ * A zero field lets the library choose.  Results never depend on it. */
 typedef struct {
     int32_t lanes_per_walk;
     int32_t waves_per_block;
+    int32_t strategy;
 } tsf_launch;
 
 typedef struct tsf_ctx tsf_ctx;

@@ -7,10 +7,10 @@
 #include <cstring>
 
 namespace tsfk {
-KernelFn pick_kernel_w0_z0(int g, int s);
-KernelFn pick_kernel_w0_z1(int g, int s);
-KernelFn pick_kernel_w1_z0(int g, int s);
-KernelFn pick_kernel_w1_z1(int g, int s);
+KernelFn pick_kernel_w0_z0(int g, int s, bool ap);
+KernelFn pick_kernel_w0_z1(int g, int s, bool ap);
+KernelFn pick_kernel_w1_z0(int g, int s, bool ap);
+KernelFn pick_kernel_w1_z1(int g, int s, bool ap);
 }  // namespace tsfk
 
 namespace {
@@ -122,10 +122,10 @@ __global__ void __launch_bounds__(256) verify_kernel(const tsf_walk_header *hdr,
 // ---------------------------------------------------------------------------
 // host side: kernel table and launch
 // ---------------------------------------------------------------------------
-KernelFn pick_kernel(int g, int s, bool wide, bool z2)
+KernelFn pick_kernel(int g, int s, bool wide, bool z2, bool ap)
 {
-    if (wide) return z2 ? pick_kernel_w1_z1(g, s) : pick_kernel_w1_z0(g, s);
-    return z2 ? pick_kernel_w0_z1(g, s) : pick_kernel_w0_z0(g, s);
+    if (wide) return z2 ? pick_kernel_w1_z1(g, s, ap) : pick_kernel_w1_z0(g, s, ap);
+    return z2 ? pick_kernel_w0_z1(g, s, ap) : pick_kernel_w0_z0(g, s, ap);
 }
 
 int slots_for(int cap, int g)
@@ -208,21 +208,30 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
         return tsf_fail(TSF_E_ARG, "a probability threshold exceeds 2^32");
     if (n_iters < 0) return tsf_fail(TSF_E_ARG, "n_iters < 0");
     if (b->n_walks == 0 || n_iters == 0) return TSF_OK;
-    int g = launch && launch->lanes_per_walk ? launch->lanes_per_walk : (b->capacity <= 64 ? 8 : 64);
+    int strategy = launch ? launch->strategy : 0;
+    if (strategy < 0 || strategy > 2) return tsf_fail(TSF_E_ARG, "strategy %d not in 0..2", strategy);
+    if (strategy == 0) strategy = b->capacity <= 64 ? 1 : 2;
+    const bool ap = strategy == 1;
+    if (ap && b->capacity > 64)
+        return tsf_fail(TSF_E_CAPACITY, "the attempt-parallel strategy needs capacity <= 64");
+    int g = launch && launch->lanes_per_walk ? launch->lanes_per_walk : (ap ? 8 : 64);
     int wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4;
     if (g != 8 && g != 16 && g != 32 && g != 64)
         return tsf_fail(TSF_E_ARG, "lanes_per_walk %d not in {8,16,32,64}", g);
+    if (ap && g == 64)
+        return tsf_fail(TSF_E_ARG, "the attempt-parallel strategy uses 8, 16 or 32 lanes per walk");
     if (wpb < 1 || wpb > 4) return tsf_fail(TSF_E_ARG, "waves_per_block %d not in 1..4", wpb);
     const int s = slots_for(b->capacity, g);
     if (s < 0)
         return tsf_fail(TSF_E_CAPACITY, "capacity %d needs more than 8 slots at %d lanes/walk",
                         b->capacity, g);
     const bool wide = b->max_len > 32;
-    KernelFn fn = pick_kernel(g, s, wide, b->mode == TSF_Z2);
+    KernelFn fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, ap);
     if (!fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
     const size_t word = wide ? 8 : 4;
     const int walks_per_wave = 64 / g;
-    const size_t lds = (size_t)wpb * walks_per_wave * b->capacity * 6 * word;
+    const int cap2 = b->capacity + (b->capacity & 1);
+    const size_t lds = (size_t)wpb * walks_per_wave * cap2 * 6 * word;
     if (lds > 160 * 1024)
         return tsf_fail(TSF_E_CAPACITY, "%zu bytes of LDS per workgroup exceed 160 KiB", lds);
     KArgs a;
@@ -242,6 +251,7 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
     a.rec_cap = b->rec_cap;
     a.mode = b->mode;
     a.max_len = b->max_len;
+    a.cap2 = cap2;
     a.hdr = b->hdr;
     a.cur = b->cur;
     a.best = b->best;

@@ -1,24 +1,35 @@
 // walk_kernel.h -- batched ternary flip-graph random walks on gfx950 (MI355X).
 //
-// One walk is owned by a group of G lanes of a 64-lane wavefront (G = 8, 16,
-// 32 or 64, i.e. 64/G walks per wavefront).  The walk's current scheme lives
-// in LDS in the one-bit form of Sec. 3.5.1 (per term: u, v, w as digit/sign
-// mask pairs; 32-bit words when every factor has at most 32 entries).  Term k
-// is examined by lane k mod G, so one partner search over r terms costs
-// ceil(r/G) masked compares per lane plus one group ballot per slot.  All
-// per-walk scalars (rank, counters, random words) are replicated in every
-// lane of the group, which keeps control flow uniform inside a group; groups
-// of one wavefront diverge freely because no instruction mixes lanes of
-// different groups.  HBM is read and written only at the start and end of a
-// call (coalesced over the group's lanes) and when the best scheme changes.
+// One walk is owned by a group of G lanes of a 64-lane wavefront (64/G walks
+// per wavefront).  The walk's current scheme lives in LDS in the one-bit form
+// of Sec. 3.5.1, factor-major: the (digits, signs) pair of factor X of term k
+// sits at words 2*(X*cap2 + k), so the same factor of consecutive terms is
+// contiguous (two terms per 128-bit LDS read with 32-bit masks).  Per-walk
+// scalars (rank, counters, random words) are replicated in every lane of the
+// group, which keeps control flow uniform inside a group; groups of one
+// wavefront diverge freely because no instruction mixes lanes of different
+// groups.  HBM is read and written only at the start and end of a call and
+// when the best scheme changes.
 //
 // The iteration follows Algorithm 1 (RandomWalk kernel, Sec. 3.4.2): a flip
 // (Sec. 3.3.1) with ternary-safe arithmetic (Sec. 3.5.2) and sign
 // normalisation (Sec. 3.6), zero-term removal, the best-scheme update,
 // reduction with probability p_reduce, expand with probability p_expand near
-// the best rank, and a plateau restart.  The random words come from one
-// Philox4x32-10 block per (iteration, attempt, domain), so a skipped draw
-// never shifts the stream and results do not depend on G or the launch.
+// the best rank, and a plateau restart.  Every random word comes from one
+// Philox4x32-10 block per (iteration, attempt, domain): at the start of an
+// iteration lane q < G-1 of the group draws the block of flip attempt q and
+// lane G-1 the per-iteration gate block, so the draws run in parallel and a
+// skipped draw never shifts the stream.
+//
+// Two strategies search for a flip; both take the first attempt (in attempt
+// order) that has a valid partner, so their results are identical:
+//  * attempt-parallel (AP, schemes of at most 64 terms): each lane evaluates
+//    one random attempt (term i, factor kind X) against all terms -- a match
+//    scan over the X factors (two terms per LDS read), then the validity of
+//    the two roles for the few matches only;
+//  * term-parallel (TP, any size): attempts run one after another and the G
+//    lanes split the terms (slot q of lane l is term q*G + l), with one group
+//    ballot per slot and role.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -41,7 +52,7 @@ struct KArgs {
     int32_t rec_cap;
     int32_t mode;
     int32_t max_len;
-    int32_t pad;
+    int32_t cap2;  // LDS stride per factor kind: cap rounded up to even
     tsf_walk_header *hdr;
     uint64_t *cur;
     uint64_t *best;
@@ -50,7 +61,8 @@ struct KArgs {
 };
 
 // role permutations (X,Y,Z) of (U,V,W), lexicographic
-static __constant__ int8_t kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+static __constant__ int8_t kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
+                                          {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
 template <typename T>
 struct TV {
@@ -73,15 +85,6 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T>
-__device__ __forceinline__ int ctz_t(T x)
-{
-    if constexpr (sizeof(T) == 8)
-        return __builtin_ctzll(x);
-    else
-        return __builtin_ctz(x);
-}
-
 __device__ __forceinline__ int popc64(uint64_t x) { return __builtin_popcountll(x); }
 
 // index of the c-th (0-based) set bit of m (m has more than c bits set)
@@ -91,12 +94,13 @@ __device__ __forceinline__ int kth_bit(uint64_t m, int c)
     return __builtin_ctzll(m);
 }
 
-template <int G, int S, typename T, bool Z2>
+template <int G, int S, typename T, bool Z2, bool AP>
 struct Walker {
     // group geometry
     int gl;      // lane within the group
     int gshift;  // first lane of the group within the wavefront
-    T *lds;      // this walk's terms: word x of term k at lds[k*6 + x]
+    int cap2;
+    T *lds;
     // walk scalars, identical in every lane of the group
     uint64_t seed;
     int r, r_cap, best_rank, start_rank, target, n_rec;
@@ -104,6 +108,8 @@ struct Walker {
     uint32_t cnt[C_NUM];
     const KArgs *a;
     int64_t walk;
+    // this iteration's Philox block of this lane (attempt gl, or the gate)
+    Philox4 pb;
 
     __device__ __forceinline__ uint64_t gballot(bool p) const
     {
@@ -113,16 +119,21 @@ struct Walker {
         else
             return (m >> gshift) & ((1ull << G) - 1);
     }
+    __device__ __forceinline__ uint32_t from_lane(uint32_t v, int lane) const
+    {
+        return (uint32_t)__shfl((int)v, gshift + lane);
+    }
 
+    __device__ __forceinline__ int idx(int k, int X) const { return (X * cap2 + k) * 2; }
     __device__ __forceinline__ TV<T> ld(int k, int X) const
     {
-        const T *q = lds + k * 6 + 2 * X;
+        const T *q = lds + idx(k, X);
         return TV<T>{q[0], q[1]};
     }
     __device__ __forceinline__ void st(int k, int X, TV<T> v)
     {
         if (gl == 0) {
-            T *q = lds + k * 6 + 2 * X;
+            T *q = lds + idx(k, X);
             q[0] = v.d;
             q[1] = v.s;
         }
@@ -148,28 +159,33 @@ struct Walker {
         return 0;
     }
 
-    // Sec. 3.6: first non-zero of u, then of v, made positive; w absorbs.
+    // Sec. 3.6 on a term held in registers: first non-zero of u, then of v,
+    // made positive; w absorbs.
+    __device__ __forceinline__ static void normalise_regs(TV<T> (&f)[3])
+    {
+        if constexpr (!Z2) {
+            const T lu = f[0].d & (~f[0].d + 1);
+            if (f[0].s & lu) {
+                f[0].s ^= f[0].d;
+                f[2].s ^= f[2].d;
+            }
+            const T lv = f[1].d & (~f[1].d + 1);
+            if (f[1].s & lv) {
+                f[1].s ^= f[1].d;
+                f[2].s ^= f[2].d;
+            }
+        }
+    }
     __device__ void normalise(int k)
     {
         if constexpr (Z2) return;
-        TV<T> u = ld(k, 0), v = ld(k, 1), w = ld(k, 2);
-        bool ch = false;
-        T lu = u.d & (~u.d + 1);
-        if (u.s & lu) {
-            u.s ^= u.d;
-            w.s ^= w.d;
-            ch = true;
-        }
-        T lv = v.d & (~v.d + 1);
-        if (v.s & lv) {
-            v.s ^= v.d;
-            w.s ^= w.d;
-            ch = true;
-        }
-        if (ch) {
-            st(k, 0, u);
-            st(k, 1, v);
-            st(k, 2, w);
+        TV<T> f[3] = {ld(k, 0), ld(k, 1), ld(k, 2)};
+        const T s0 = f[0].s, s1 = f[1].s;
+        normalise_regs(f);
+        if (f[0].s != s0 || f[1].s != s1) {
+            st(k, 0, f[0]);
+            st(k, 1, f[1]);
+            st(k, 2, f[2]);
         }
         wave_lds_sync();
     }
@@ -186,7 +202,10 @@ struct Walker {
         if (tr0 == h) tr0 = -1;
         if (tr1 == h) tr1 = -1;
         if (h != last) {
-            if (gl < 6) lds[h * 6 + gl] = lds[last * 6 + gl];
+            if (gl < 6) {
+                const int X = gl >> 1, w = gl & 1;
+                lds[idx(h, X) + w] = lds[idx(last, X) + w];
+            }
             if (tr0 == last) tr0 = h;
             if (tr1 == last) tr1 = h;
         }
@@ -194,10 +213,45 @@ struct Walker {
         r = last;
     }
 
-    // Candidate partners of (i, X): lane-parallel over the terms, one
-    // ballot per slot and role.  m0/m1: role 0/1 masks (bit = lane of slot q).
-    __device__ void candidates(int i, int X, uint64_t (&m0)[S], uint64_t (&m1)[S], int &n0,
-                               int &n1) const
+    // Flip (Sec. 3.3.1): x_j = sigma x_i; y_i += sigma y_j; z_j -= z_i;
+    // (Y,Z) = the other kinds in U<V<W order, swapped for role 1.
+    __device__ void apply_flip(int i, int j, int X, int role)
+    {
+        const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
+        const int Y = role ? B : A, Z = role ? A : B;
+        const int sg = rel(ld(i, X), ld(j, X), X);
+        TV<T> ny, nz;
+        axpy(sg, ld(i, Y), ld(j, Y), ny);
+        axpy(-1, ld(j, Z), ld(i, Z), nz);
+        st(i, Y, ny);
+        st(j, Z, nz);
+        wave_lds_sync();
+        normalise(i);
+        normalise(j);
+    }
+
+    // random words of flip attempt `att`: from the lane that drew them in this
+    // iteration's batch, or drawn now (uniformly by the whole group)
+    __device__ __forceinline__ void attempt_words(int att, uint32_t &w0, uint32_t &w1,
+                                                  uint32_t &w2)
+    {
+        if (att < G - 1) {
+            w0 = from_lane(pb.x[0], att);
+            w1 = from_lane(pb.x[1], att);
+            w2 = from_lane(pb.x[2], att);
+        } else {
+            const Philox4 w = walk_block(seed, t, (uint32_t)att, 0);
+            w0 = w.x[0];
+            w1 = w.x[1];
+            w2 = w.x[2];
+        }
+    }
+
+    // ------------------------------------------------------------------ TP
+    // Candidate partners of (i, X): lane-parallel over the terms, one ballot
+    // per slot and role.  m0/m1: role 0/1 masks (bit = lane of slot q).
+    __device__ void candidates_tp(int i, int X, uint64_t (&m0)[S], uint64_t (&m1)[S], int &n0,
+                                  int &n1) const
     {
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
         const TV<T> xi = ld(i, X), Ai = ld(i, A), Bi = ld(i, B);
@@ -226,7 +280,7 @@ struct Walker {
         }
     }
 
-    __device__ __forceinline__ int select(const uint64_t (&m)[S], int c) const
+    __device__ __forceinline__ int select_tp(const uint64_t (&m)[S], int c) const
     {
         int j = -1;
 #pragma unroll
@@ -242,52 +296,127 @@ struct Walker {
         return j;
     }
 
-    // Flip (Sec. 3.3.1): x_j = sigma x_i; y_i += sigma y_j; z_j -= z_i;
-    // (Y,Z) = the other kinds in U<V<W order, swapped for role 1.
-    __device__ void apply_flip(int i, int j, int X, int role)
+    // ------------------------------------------------------------------ AP
+    // Partners of (i, X) for this lane alone, over all r <= 64 terms: bit k of
+    // m0/m1 is set when (k, role 0/1) is a valid flip partner.
+    __device__ void candidates_ap(int i, int X, uint64_t &m0, uint64_t &m1) const
     {
+        const TV<T> xi = ld(i, X);
+        const T nsi = xi.s ^ xi.d;  // signs of -x_i
+        const bool negw = !Z2 && X == 2;
+        const T *col = lds + idx(0, X);
+        uint64_t match = 0;
+        for (int k = 0; k < r; k += 2) {
+            // factor X of terms k and k+1 (the LDS stride is even, so k+1 stays
+            // inside this walk's region; bits at or beyond r are masked below)
+            const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2], s1 = col[2 * k + 3];
+            const bool e0 = d0 == xi.d && (s0 == xi.s || (negw && s0 == nsi));
+            const bool e1 = d1 == xi.d && (s1 == xi.s || (negw && s1 == nsi));
+            match |= ((uint64_t)e0 << k) | ((uint64_t)e1 << (k + 1));
+        }
+        match &= (r >= 64 ? ~0ull : ((1ull << r) - 1)) & ~(1ull << i);
+        m0 = m1 = 0;
+        if (match == 0) return;
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
-        const int Y = role ? B : A, Z = role ? A : B;
-        const int sg = rel(ld(i, X), ld(j, X), X);
-        TV<T> ny, nz;
-        axpy(sg, ld(i, Y), ld(j, Y), ny);
-        axpy(-1, ld(j, Z), ld(i, Z), nz);
-        st(i, Y, ny);
-        st(j, Z, nz);
-        wave_lds_sync();
-        normalise(i);
-        normalise(j);
+        const TV<T> Ai = ld(i, A), Bi = ld(i, B);
+        for (uint64_t mm = match; mm; mm &= mm - 1) {
+            const int k = __builtin_ctzll(mm);
+            const int sg = (Z2 || ld(k, X).s == xi.s) ? 1 : -1;
+            const TV<T> Ak = ld(k, A), Bk = ld(k, B);
+            TV<T> o1, o2;
+            const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
+            const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
+            m0 |= (uint64_t)(a1 && b1) << k;
+            m1 |= (uint64_t)(a2 && b2) << k;
+        }
     }
 
+    // ------------------------------------------------------------------ flip
     __device__ bool try_flip(int &fi, int &fj)
     {
         if (r < 2) return false;
+        const int T_ = a->flip_tries;
+        if constexpr (AP) {
+            constexpr int P = G - 1;  // attempts per batch
+            for (int base = 0; base < T_; base += P) {
+                const int att = base + gl;
+                const bool active = gl < P && att < T_;
+                uint32_t w0, w1, w2;
+                if (base == 0) {
+                    w0 = pb.x[0];
+                    w1 = pb.x[1];
+                    w2 = pb.x[2];
+                } else {
+                    const Philox4 w = walk_block(seed, t, (uint32_t)att, 0);
+                    w0 = w.x[0];
+                    w1 = w.x[1];
+                    w2 = w.x[2];
+                }
+                const int i = (int)below(w0, (uint32_t)r);
+                const int X = (int)below(w1, 3u);
+                uint64_t m0 = 0, m1 = 0;
+                if (active) candidates_ap(i, X, m0, m1);
+                const int n0 = popc64(m0), n = n0 + popc64(m1);
+                const uint64_t ok = gballot(n > 0);
+                if (ok) {
+                    const int win = __builtin_ctzll(ok);
+                    uint32_t pick = 0;
+                    if (gl == win) {
+                        int c = (int)below(w2, (uint32_t)n);
+                        const int role = c >= n0;
+                        if (role) c -= n0;
+                        const int j = kth_bit(role ? m1 : m0, c);
+                        pick = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)X << 16) |
+                               ((uint32_t)role << 18);
+                    }
+                    pick = from_lane(pick, win);
+                    const int pi = pick & 0xFF, pj = (pick >> 8) & 0xFF;
+                    cnt[C_ATTEMPTS] += (uint32_t)(base + win + 1);
+                    apply_flip(pi, pj, (pick >> 16) & 3, (pick >> 18) & 1);
+                    fi = pi;
+                    fj = pj;
+                    return true;
+                }
+            }
+            cnt[C_ATTEMPTS] += (uint32_t)T_;
+            return fallback_ap(fi, fj);
+        } else {
+            uint64_t m0[S], m1[S];
+            int n0, n1;
+            for (int att = 0; att < T_; ++att) {
+                uint32_t w0, w1, w2;
+                attempt_words(att, w0, w1, w2);
+                cnt[C_ATTEMPTS]++;
+                const int i = (int)below(w0, (uint32_t)r);
+                const int X = (int)below(w1, 3u);
+                candidates_tp(i, X, m0, m1, n0, n1);
+                const int n = n0 + n1;
+                if (n > 0) {
+                    int c = (int)below(w2, (uint32_t)n);
+                    const int role = c >= n0;
+                    if (role) c -= n0;
+                    const int j = role ? select_tp(m1, c) : select_tp(m0, c);
+                    apply_flip(i, j, X, role);
+                    fi = i;
+                    fj = j;
+                    return true;
+                }
+            }
+            return fallback_tp(fi, fj);
+        }
+    }
+
+    // Exhaustive search when every attempt failed: all valid (i, X, role, j)
+    // in that nesting order, entry U(w0, count) of block (t, flip_tries, 0).
+    __device__ bool fallback_tp(int &fi, int &fj)
+    {
+        cnt[C_FALLBACKS]++;
         uint64_t m0[S], m1[S];
         int n0, n1;
-        for (int att = 0; att < a->flip_tries; ++att) {
-            const Philox4 w = walk_block(seed, t, (uint32_t)att, 0);
-            cnt[C_ATTEMPTS]++;
-            const int i = (int)below(w.x[0], (uint32_t)r);
-            const int X = (int)below(w.x[1], 3u);
-            candidates(i, X, m0, m1, n0, n1);
-            const int n = n0 + n1;
-            if (n > 0) {
-                int c = (int)below(w.x[2], (uint32_t)n);
-                const int role = c >= n0;
-                if (role) c -= n0;
-                const int j = role ? select(m1, c) : select(m0, c);
-                apply_flip(i, j, X, role);
-                fi = i;
-                fj = j;
-                return true;
-            }
-        }
-        // exhaustive fallback over (i, X, role, j)
-        cnt[C_FALLBACKS]++;
         uint32_t total = 0;
         for (int i = 0; i < r; ++i)
             for (int X = 0; X < 3; ++X) {
-                candidates(i, X, m0, m1, n0, n1);
+                candidates_tp(i, X, m0, m1, n0, n1);
                 total += (uint32_t)(n0 + n1);
             }
         if (total == 0) return false;
@@ -295,9 +424,9 @@ struct Walker {
         uint32_t pick = below(w.x[0], total);
         for (int i = 0; i < r; ++i)
             for (int X = 0; X < 3; ++X) {
-                candidates(i, X, m0, m1, n0, n1);
+                candidates_tp(i, X, m0, m1, n0, n1);
                 if (pick < (uint32_t)n0) {
-                    const int j = select(m0, (int)pick);
+                    const int j = select_tp(m0, (int)pick);
                     apply_flip(i, j, X, 0);
                     fi = i;
                     fj = j;
@@ -305,7 +434,7 @@ struct Walker {
                 }
                 pick -= (uint32_t)n0;
                 if (pick < (uint32_t)n1) {
-                    const int j = select(m1, (int)pick);
+                    const int j = select_tp(m1, (int)pick);
                     apply_flip(i, j, X, 1);
                     fi = i;
                     fj = j;
@@ -316,6 +445,63 @@ struct Walker {
         return false;  // not reached: total counted every candidate
     }
 
+    // The same search with the (i, X) pairs p = 3i + X spread over the lanes:
+    // pair p is handled by lane p mod G in round p / G.
+    __device__ bool fallback_ap(int &fi, int &fj)
+    {
+        cnt[C_FALLBACKS]++;
+        const int npairs = 3 * r;
+        uint32_t total = 0;
+        for (int p0 = 0; p0 < npairs; p0 += G) {
+            const int p = p0 + gl;
+            uint64_t m0 = 0, m1 = 0;
+            if (p < npairs) candidates_ap(p / 3, p % 3, m0, m1);
+            uint32_t c = (uint32_t)(popc64(m0) + popc64(m1));
+            // group sum
+            for (int off = 1; off < G; off <<= 1) c += (uint32_t)__shfl_xor((int)c, off, G);
+            total += c;
+        }
+        if (total == 0) return false;
+        const Philox4 w = walk_block(seed, t, (uint32_t)a->flip_tries, 0);
+        uint32_t pick = below(w.x[0], total);
+        for (int p0 = 0; p0 < npairs; p0 += G) {
+            const int p = p0 + gl;
+            uint64_t m0 = 0, m1 = 0;
+            if (p < npairs) candidates_ap(p / 3, p % 3, m0, m1);
+            const uint32_t c = (uint32_t)(popc64(m0) + popc64(m1));
+            // inclusive scan over the lanes of the group
+            uint32_t incl = c;
+            for (int off = 1; off < G; off <<= 1) {
+                const uint32_t v = (uint32_t)__shfl_up((int)incl, off, G);
+                if (gl >= off) incl += v;
+            }
+            const uint32_t round_total = from_lane(incl, G - 1);
+            if (pick < round_total) {
+                const bool mine = pick < incl && pick >= incl - c;
+                const int win = __builtin_ctzll(gballot(mine));
+                uint32_t packed = 0;
+                if (gl == win) {
+                    int cc = (int)(pick - (incl - c));
+                    const int n0 = popc64(m0);
+                    const int role = cc >= n0;
+                    if (role) cc -= n0;
+                    const int j = kth_bit(role ? m1 : m0, cc);
+                    packed = (uint32_t)(p / 3) | ((uint32_t)j << 8) | ((uint32_t)(p % 3) << 16) |
+                             ((uint32_t)role << 18);
+                }
+                packed = from_lane(packed, win);
+                const int pi = packed & 0xFF, pj = (packed >> 8) & 0xFF;
+                apply_flip(pi, pj, (packed >> 16) & 3, (packed >> 18) & 1);
+                fi = pi;
+                fj = pj;
+                return true;
+            }
+            pick -= round_total;
+        }
+        return false;  // not reached
+    }
+
+    // ------------------------------------------------------------------ reduce
     // Reduction (Sec. 3.3.1) between terms t and k: shared (u,v) merges w,
     // shared (u, +-w) merges v, shared (v, +-w) merges u; returns the kind
     // merged or -1 when no merge keeps the coefficients in the set.
@@ -330,6 +516,27 @@ struct Walker {
         return -1;
     }
 
+    // first term k (ascending, k != tt_i) that merges with term tt_i, or -1
+    __device__ int find_merge(int tt_i, const TV<T> (&tt)[3]) const
+    {
+        int k = -1;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            bool ok = false;
+            if (q * G < r) {
+                const int kk = q * G + gl;
+                if (kk < r && kk != tt_i) {
+                    const TV<T> tk[3] = {ld(kk, 0), ld(kk, 1), ld(kk, 2)};
+                    TV<T> o;
+                    ok = merge_kind(tt, tk, o) >= 0;
+                }
+            }
+            const uint64_t mk = gballot(ok);
+            if (k < 0 && mk) k = q * G + __builtin_ctzll(mk);
+        }
+        return k;
+    }
+
     // reduce the terms modified by the flip, cascading; returns merges
     __device__ int reduce(int &tr0, int &tr1)
     {
@@ -339,21 +546,7 @@ struct Walker {
                 const int tt_i = qq == 0 ? tr0 : tr1;
                 if (tt_i < 0) break;
                 TV<T> tt[3] = {ld(tt_i, 0), ld(tt_i, 1), ld(tt_i, 2)};
-                int k = -1;
-#pragma unroll
-                for (int q = 0; q < S; ++q) {
-                    bool ok = false;
-                    if (q * G < r) {
-                        const int kk = q * G + gl;
-                        if (kk < r && kk != tt_i) {
-                            TV<T> tk[3] = {ld(kk, 0), ld(kk, 1), ld(kk, 2)};
-                            TV<T> o;
-                            ok = merge_kind(tt, tk, o) >= 0;
-                        }
-                    }
-                    const uint64_t mk = gballot(ok);
-                    if (k < 0 && mk) k = q * G + __builtin_ctzll(mk);
-                }
+                const int k = find_merge(tt_i, tt);
                 if (k < 0) break;
                 ++merges;
                 TV<T> tk[3] = {ld(k, 0), ld(k, 1), ld(k, 2)};
@@ -364,27 +557,33 @@ struct Walker {
                 if (qq == 0 && tr1 == k) tr1 = -1;
                 if (qq == 1 && tr0 == k) tr0 = -1;
                 if (md.d == 0) {
-                    if (qq == 0) tr0 = -1; else tr1 = -1;
+                    if (qq == 0)
+                        tr0 = -1;
+                    else
+                        tr1 = -1;
                     swap_remove(hi, tr0, tr1);
                     swap_remove(lo, tr0, tr1);
                     break;
                 }
-                if (lo != tt_i) {
-                    st(lo, 0, tt[0]);
-                    st(lo, 1, tt[1]);
-                    st(lo, 2, tt[2]);
-                }
-                st(lo, kind, md);
+                TV<T> nt[3] = {kind == 0 ? md : tt[0], kind == 1 ? md : tt[1],
+                               kind == 2 ? md : tt[2]};
+                normalise_regs(nt);
+                st(lo, 0, nt[0]);
+                st(lo, 1, nt[1]);
+                st(lo, 2, nt[2]);
                 wave_lds_sync();
-                normalise(lo);
-                if (qq == 0) tr0 = lo; else tr1 = lo;
+                if (qq == 0)
+                    tr0 = lo;
+                else
+                    tr1 = lo;
                 swap_remove(hi, tr0, tr1);
             }
         }
         return merges;
     }
 
-    // expand (plus or split, Sec. 3.3.1), up to eight random attempts
+    // ------------------------------------------------------------------ expand
+    // plus or split (Sec. 3.3.1), up to eight random attempts
     __device__ bool expand()
     {
         if (r >= r_cap || r < 2) return false;
@@ -433,12 +632,21 @@ struct Walker {
         return false;
     }
 
-    __device__ void copy_best()
+    // ------------------------------------------------------------------ HBM
+    __device__ void load_scheme(const uint64_t *src, int rr)
     {
-        uint64_t *dst = a->best + (size_t)walk * a->cap * 6;
-        for (int k = gl; k < r; k += G)
-#pragma unroll
-            for (int x = 0; x < 6; ++x) dst[k * 6 + x] = (uint64_t)lds[k * 6 + x];
+        for (int e = gl; e < rr * 6; e += G) {
+            const int k = e / 6, x = e % 6;
+            lds[idx(k, x >> 1) + (x & 1)] = (T)src[e];
+        }
+        wave_lds_sync();
+    }
+    __device__ void store_scheme(uint64_t *dst) const
+    {
+        for (int e = gl; e < r * 6; e += G) {
+            const int k = e / 6, x = e % 6;
+            dst[e] = (uint64_t)lds[idx(k, x >> 1) + (x & 1)];
+        }
     }
 
     __device__ void restart_check()
@@ -448,10 +656,7 @@ struct Walker {
             const uint64_t *src = (from_best ? (const uint64_t *)a->best : a->start) +
                                   (size_t)walk * a->cap * 6;
             const int rr = from_best ? best_rank : start_rank;
-            for (int k = gl; k < rr; k += G)
-#pragma unroll
-                for (int x = 0; x < 6; ++x) lds[k * 6 + x] = (T)src[k * 6 + x];
-            wave_lds_sync();
+            load_scheme(src, rr);
             r = rr;
             plateau_start = t;
             cnt[C_RESTARTS]++;
@@ -461,6 +666,11 @@ struct Walker {
     __device__ void iteration()
     {
         cnt[C_ITERS]++;
+        {
+            // this iteration's draws: lane q < G-1 -> flip attempt q, lane G-1 -> gates
+            const bool gate_lane = gl == G - 1;
+            pb = walk_block(seed, t, gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
+        }
         int fi = -1, fj = -1;
         if (!try_flip(fi, fj)) {
             // Algorithm 1: no flip -> expand, continue
@@ -483,18 +693,12 @@ struct Walker {
             swap_remove(fj, tr0, tr1);
             cnt[C_ZERO_REMOVED]++;
         }
-        // gates: block (t, 0, 1), drawn only when one of them can matter
-        uint32_t g0 = 0, g1 = 0, g2 = 0;
-        const bool need = (r == best_rank && a->t_eq > 0) || a->t_reduce <= 0xFFFFFFFFull ||
-                          a->t_expand > 0;
-        if (need) {
-            const Philox4 g = walk_block(seed, t, 0u, 1u);
-            g0 = g.x[0];
-            g1 = g.x[1];
-            g2 = g.x[2];
-        }
+        // gates: block (t, 0, 1), drawn by the last lane of the group
+        const uint32_t g0 = from_lane(pb.x[0], G - 1);
+        const uint32_t g1 = from_lane(pb.x[1], G - 1);
+        const uint32_t g2 = from_lane(pb.x[2], G - 1);
         if (r < best_rank) {
-            copy_best();
+            store_scheme(a->best + (size_t)walk * a->cap * 6);
             best_rank = r;
             plateau_start = t;
             if (gl == 0 && n_rec < a->rec_cap) {
@@ -506,7 +710,7 @@ struct Walker {
             n_rec++;
             cnt[C_IMPROVEMENTS]++;
         } else if (r == best_rank && (uint64_t)g0 < a->t_eq) {
-            copy_best();
+            store_scheme(a->best + (size_t)walk * a->cap * 6);
             cnt[C_EQ_ACCEPTS]++;
         }
         if ((uint64_t)g1 < a->t_reduce) cnt[C_MERGES] += (uint32_t)reduce(tr0, tr1);
@@ -520,7 +724,7 @@ __device__ __forceinline__ int flen(int m, int n, int p, int X)
     return X == 0 ? m * n : X == 1 ? n * p : p * m;
 }
 
-template <int G, int S, typename T, bool Z2>
+template <int G, int S, typename T, bool Z2, bool AP>
 __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
 {
     extern __shared__ uint64_t smem_u64[];
@@ -532,10 +736,11 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
     const int64_t walk = ((int64_t)blockIdx.x * wpb + wave) * W + grp;
     if (walk >= a.n_walks) return;  // the whole group leaves together
 
-    Walker<G, S, T, Z2> wk;
+    Walker<G, S, T, Z2, AP> wk;
     wk.gl = lane % G;
     wk.gshift = grp * G;
-    wk.lds = smem + (size_t)(wave * W + grp) * a.cap * 6;
+    wk.cap2 = a.cap2;
+    wk.lds = smem + (size_t)(wave * W + grp) * a.cap2 * 6;
     wk.a = &a;
     wk.walk = walk;
     tsf_walk_header *h = a.hdr + walk;
@@ -547,7 +752,7 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
                       lmax <= (int)(8 * sizeof(T)) && h->mode == (Z2 ? 1 : 0) &&
                       h->r_cap <= a.cap && h->rank >= 0 && h->rank <= h->r_cap &&
                       h->best_rank >= 0 && h->best_rank <= a.cap && h->start_rank >= 0 &&
-                      h->start_rank <= a.cap;
+                      h->start_rank <= a.cap && (!AP || a.cap <= 64);
     if (!sane || done != 0) {
         if (!sane && wk.gl == 0 && done == 0) h->done = -1;
         return;
@@ -563,12 +768,7 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
     wk.plateau_start = h->plateau_start;
 #pragma unroll
     for (int c = 0; c < C_NUM; ++c) wk.cnt[c] = 0;
-
-    const uint64_t *src = a.cur + (size_t)walk * a.cap * 6;
-    for (int k = wk.gl; k < wk.r; k += G)
-#pragma unroll
-        for (int x = 0; x < 6; ++x) wk.lds[k * 6 + x] = (T)src[k * 6 + x];
-    wave_lds_sync();
+    wk.load_scheme(a.cur + (size_t)walk * a.cap * 6, wk.r);
 
     for (int64_t it = 0; it < a.n_iters; ++it) {
         if (wk.best_rank <= wk.target) done = 1;
@@ -578,10 +778,7 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
     }
     if (wk.best_rank <= wk.target) done = 1;
 
-    uint64_t *dst = a.cur + (size_t)walk * a.cap * 6;
-    for (int k = wk.gl; k < wk.r; k += G)
-#pragma unroll
-        for (int x = 0; x < 6; ++x) dst[k * 6 + x] = (uint64_t)wk.lds[k * 6 + x];
+    wk.store_scheme(a.cur + (size_t)walk * a.cap * 6);
     if (wk.gl == 0) {
         h->rank = wk.r;
         h->best_rank = wk.best_rank;

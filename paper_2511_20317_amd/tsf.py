@@ -57,7 +57,8 @@ class WalkBatchC(C.Structure):
 
 
 class Launch(C.Structure):
-    _fields_ = [("lanes_per_walk", C.c_int32), ("waves_per_block", C.c_int32)]
+    _fields_ = [("lanes_per_walk", C.c_int32), ("waves_per_block", C.c_int32),
+                ("strategy", C.c_int32)]
 
 
 # numpy view of tsf_walk_header (160 bytes)
@@ -304,8 +305,8 @@ class WalkBatch:
         check(lib().tsf_walk_init(ctx.ptr, C.byref(self.c()), self._stream()))
 
     def walk(self, ctx: Context, prm: WalkParams, n_iters: int, lanes_per_walk=0,
-             waves_per_block=0):
-        la = Launch(lanes_per_walk, waves_per_block)
+             waves_per_block=0, strategy=0):
+        la = Launch(lanes_per_walk, waves_per_block, strategy)
         check(lib().tsf_walk(ctx.ptr, C.byref(prm), C.byref(self.c()), int(n_iters),
                              C.byref(la), self._stream()))
 

@@ -25,11 +25,12 @@ def _std(m, n, p, mode=tsf.TSF_TERNARY):
     return tsf.init_scheme(m, n, p, mode)
 
 
-def _run(ctx, groups, prm, n_iters, splits=None, lanes=0, wpb=0, rec_cap=64, capacity=None):
+def _run(ctx, groups, prm, n_iters, splits=None, lanes=0, wpb=0, rec_cap=64, capacity=None,
+         strategy=0):
     b = tsf.WalkBatch(groups, capacity=capacity, rec_cap=rec_cap)
     b.init(ctx)
     for chunk in (splits or [n_iters]):
-        b.walk(ctx, prm, chunk, lanes, wpb)
+        b.walk(ctx, prm, chunk, lanes, wpb, strategy)
     _sync()
     return b
 
@@ -47,13 +48,27 @@ def test_config1_2x2x2_all_walks(ctx):
     assert (nv == 0).all()
 
 
-@pytest.mark.parametrize("lanes,wpb", [(8, 4), (16, 2), (32, 1), (64, 4)])
-def test_lanes_per_walk_and_round_split_invariance(ctx, lanes, wpb):
+@pytest.mark.parametrize("lanes,wpb,strategy", [(8, 4, 1), (16, 2, 1), (32, 1, 1), (8, 4, 2),
+                                                (16, 2, 2), (32, 1, 2), (64, 4, 2)])
+def test_launch_shape_and_round_split_invariance(ctx, lanes, wpb, strategy):
+    """Both flip-search strategies, every lanes-per-walk choice, rounds split
+    unevenly: identical to the oracle."""
     groups = [(_std(3, 3, 3), 48, 35, 23)]
     prm = tsf.walk_params(base_seed=7, max_iters=3000, plateau=1000, t_expand=1 << 28)
     splits = [1, 999, 1500, 500]
-    b = _run(ctx, groups, prm, 3000, splits=splits, lanes=lanes, wpb=wpb)
-    compare(b, run_oracle(groups, prm, range(48), 3000), "333 G=%d" % lanes)
+    b = _run(ctx, groups, prm, 3000, splits=splits, lanes=lanes, wpb=wpb, strategy=strategy)
+    compare(b, run_oracle(groups, prm, range(48), 3000), "333 G=%d s=%d" % (lanes, strategy))
+
+
+@pytest.mark.parametrize("tries", [1, 3, 16, 40])
+def test_flip_tries_across_batches(ctx, tries):
+    """Attempt batches of G-1 lanes, extra batches, and the exhaustive search."""
+    groups = [(_std(2, 2, 3), 32, 20, 0), (_std(3, 3, 3), 32, 35, 23)]
+    prm = tsf.walk_params(base_seed=21, max_iters=4000, plateau=1500, flip_tries=tries,
+                          t_expand=1 << 28)
+    for strategy in (1, 2):
+        b = _run(ctx, groups, prm, 4000, strategy=strategy, lanes=8 if strategy == 1 else 16)
+        compare(b, run_oracle(groups, prm, range(64), 4000), "tries=%d s=%d" % (tries, strategy))
 
 
 def test_3x3x3_restarts_expand_partial_reduce(ctx):
@@ -77,11 +92,12 @@ def test_mixed_formats_one_launch(ctx):
         compare(b, run_oracle(groups, prm, range(48), 2000), "mixed G=%d" % lanes)
 
 
-def test_z2_mode(ctx):
+@pytest.mark.parametrize("strategy", [1, 2])
+def test_z2_mode(ctx, strategy):
     groups = [(_std(2, 2, 2, tsf.TSF_Z2), 32, 16, 7), (_std(3, 3, 4, tsf.TSF_Z2), 16, 44, 0)]
     prm = tsf.walk_params(base_seed=5, max_iters=6000, plateau=2000, t_expand=1 << 27)
-    b = _run(ctx, groups, prm, 6000)
-    compare(b, run_oracle(groups, prm, range(48), 6000), "z2")
+    b = _run(ctx, groups, prm, 6000, strategy=strategy)
+    compare(b, run_oracle(groups, prm, range(48), 6000), "z2 s=%d" % strategy)
     assert (b.verify_device(which=0).cpu().numpy() == 0).all()
 
 
