@@ -110,6 +110,8 @@ struct Walker {
     int64_t walk;
     // this iteration's Philox block of this lane (attempt gl, or the gate)
     Philox4 pb;
+    // zero-factor flags of the two terms of the last flip
+    bool zfi, zfj;
 
     __device__ __forceinline__ uint64_t gballot(bool p) const
     {
@@ -190,11 +192,6 @@ struct Walker {
         wave_lds_sync();
     }
 
-    __device__ __forceinline__ bool has_zero(int k) const
-    {
-        return ld(k, 0).d == 0 || ld(k, 1).d == 0 || ld(k, 2).d == 0;
-    }
-
     // swap-remove slot h (the last term moves into it); tracked indices follow
     __device__ void swap_remove(int h, int &tr0, int &tr1)
     {
@@ -213,9 +210,48 @@ struct Walker {
         r = last;
     }
 
+    // factor X (runtime) of a term held in three named registers; written as
+    // selects on scalars so that no register array is indexed at run time
+    __device__ __forceinline__ static TV<T> sel3(TV<T> f0, TV<T> f1, TV<T> f2, int X)
+    {
+        TV<T> o;
+        o.d = X == 0 ? f0.d : (X == 1 ? f1.d : f2.d);
+        o.s = X == 0 ? f0.s : (X == 1 ? f1.s : f2.s);
+        return o;
+    }
+    __device__ __forceinline__ static void set3(TV<T> &f0, TV<T> &f1, TV<T> &f2, int X, TV<T> v)
+    {
+        f0.d = X == 0 ? v.d : f0.d;
+        f0.s = X == 0 ? v.s : f0.s;
+        f1.d = X == 1 ? v.d : f1.d;
+        f1.s = X == 1 ? v.s : f1.s;
+        f2.d = X == 2 ? v.d : f2.d;
+        f2.s = X == 2 ? v.s : f2.s;
+    }
+    __device__ __forceinline__ void load_term(int k, TV<T> (&f)[3]) const
+    {
+        f[0] = ld(k, 0);
+        f[1] = ld(k, 1);
+        f[2] = ld(k, 2);
+    }
+    __device__ __forceinline__ void store_term(int k, const TV<T> (&f)[3])
+    {
+        st(k, 0, f[0]);
+        st(k, 1, f[1]);
+        st(k, 2, f[2]);
+    }
+    __device__ __forceinline__ static bool zero_factor(const TV<T> (&f)[3])
+    {
+        return f[0].d == 0 || f[1].d == 0 || f[2].d == 0;
+    }
+
     // Flip (Sec. 3.3.1): x_j = sigma x_i; y_i += sigma y_j; z_j -= z_i;
-    // (Y,Z) = the other kinds in U<V<W order, swapped for role 1.
-    __device__ void apply_flip(int i, int j, int X, int role)
+    // (Y,Z) = the other kinds in U<V<W order, swapped for role 1.  Every live
+    // term is normalised and has non-zero factors (the start scheme is
+    // validated and every write keeps it so), so only y_i and z_j can become
+    // zero, and normalising term i (j) only needs y_i (z_j) and w.  Returns
+    // which of the two terms now has a zero factor.
+    __device__ void apply_flip(int i, int j, int X, int role, bool &zi, bool &zj)
     {
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
         const int Y = role ? B : A, Z = role ? A : B;
@@ -223,11 +259,27 @@ struct Walker {
         TV<T> ny, nz;
         axpy(sg, ld(i, Y), ld(j, Y), ny);
         axpy(-1, ld(j, Z), ld(i, Z), nz);
+        zi = ny.d == 0;
+        zj = nz.d == 0;
+        if constexpr (!Z2) {
+            // Sec. 3.6: a u or v factor whose first non-zero entry is -1 is
+            // negated, and w absorbs the sign
+            if (Y != 2 && (ny.s & ny.d & (~ny.d + 1))) {
+                ny.s ^= ny.d;
+                TV<T> w = ld(i, 2);
+                w.s ^= w.d;
+                st(i, 2, w);
+            }
+            if (Z != 2 && (nz.s & nz.d & (~nz.d + 1))) {
+                nz.s ^= nz.d;
+                TV<T> w = ld(j, 2);
+                w.s ^= w.d;
+                st(j, 2, w);
+            }
+        }
         st(i, Y, ny);
         st(j, Z, nz);
         wave_lds_sync();
-        normalise(i);
-        normalise(j);
     }
 
     // random words of flip attempt `att`: from the lane that drew them in this
@@ -298,36 +350,44 @@ struct Walker {
 
     // ------------------------------------------------------------------ AP
     // Partners of (i, X) for this lane alone, over all r <= 64 terms: bit k of
-    // m0/m1 is set when (k, role 0/1) is a valid flip partner.
+    // m0/m1 is set when (k, role 0/1) is a valid flip partner.  The match
+    // scan runs to the batch capacity (a wave-uniform bound, so the loop
+    // counter and the bit constants stay scalar) and masks terms >= r.
     __device__ void candidates_ap(int i, int X, uint64_t &m0, uint64_t &m1) const
     {
         const TV<T> xi = ld(i, X);
-        const T nsi = xi.s ^ xi.d;  // signs of -x_i
-        const bool negw = !Z2 && X == 2;
+        const T nsi = (!Z2 && X == 2) ? (xi.s ^ xi.d) : xi.s;  // accepted signs besides xi.s
         const T *col = lds + idx(0, X);
-        uint64_t match = 0;
-        for (int k = 0; k < r; k += 2) {
-            // factor X of terms k and k+1 (the LDS stride is even, so k+1 stays
-            // inside this walk's region; bits at or beyond r are masked below)
+        const int kend = a->cap2;  // even, uniform
+        uint32_t lo = 0, hi = 0;
+        int k = 0;
+        for (; k < kend && k < 32; k += 2) {
             const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2], s1 = col[2 * k + 3];
-            const bool e0 = d0 == xi.d && (s0 == xi.s || (negw && s0 == nsi));
-            const bool e1 = d1 == xi.d && (s1 == xi.s || (negw && s1 == nsi));
-            match |= ((uint64_t)e0 << k) | ((uint64_t)e1 << (k + 1));
+            const uint32_t b0 = 1u << k, b1 = 2u << k;
+            lo |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
+            lo |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
         }
+        for (; k < kend; k += 2) {
+            const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2], s1 = col[2 * k + 3];
+            const uint32_t b0 = 1u << (k - 32), b1 = 2u << (k - 32);
+            hi |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
+            hi |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
+        }
+        uint64_t match = ((uint64_t)hi << 32) | lo;
         match &= (r >= 64 ? ~0ull : ((1ull << r) - 1)) & ~(1ull << i);
         m0 = m1 = 0;
         if (match == 0) return;
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
         const TV<T> Ai = ld(i, A), Bi = ld(i, B);
         for (uint64_t mm = match; mm; mm &= mm - 1) {
-            const int k = __builtin_ctzll(mm);
-            const int sg = (Z2 || ld(k, X).s == xi.s) ? 1 : -1;
-            const TV<T> Ak = ld(k, A), Bk = ld(k, B);
+            const int kk = __builtin_ctzll(mm);
+            const int sg = (Z2 || ld(kk, X).s == xi.s) ? 1 : -1;
+            const TV<T> Ak = ld(kk, A), Bk = ld(kk, B);
             TV<T> o1, o2;
             const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
             const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
-            m0 |= (uint64_t)(a1 && b1) << k;
-            m1 |= (uint64_t)(a2 && b2) << k;
+            m0 |= (uint64_t)(a1 && b1) << kk;
+            m1 |= (uint64_t)(a2 && b2) << kk;
         }
     }
 
@@ -372,7 +432,7 @@ struct Walker {
                     pick = from_lane(pick, win);
                     const int pi = pick & 0xFF, pj = (pick >> 8) & 0xFF;
                     cnt[C_ATTEMPTS] += (uint32_t)(base + win + 1);
-                    apply_flip(pi, pj, (pick >> 16) & 3, (pick >> 18) & 1);
+                    apply_flip(pi, pj, (pick >> 16) & 3, (pick >> 18) & 1, zfi, zfj);
                     fi = pi;
                     fj = pj;
                     return true;
@@ -396,7 +456,7 @@ struct Walker {
                     const int role = c >= n0;
                     if (role) c -= n0;
                     const int j = role ? select_tp(m1, c) : select_tp(m0, c);
-                    apply_flip(i, j, X, role);
+                    apply_flip(i, j, X, role, zfi, zfj);
                     fi = i;
                     fj = j;
                     return true;
@@ -427,7 +487,7 @@ struct Walker {
                 candidates_tp(i, X, m0, m1, n0, n1);
                 if (pick < (uint32_t)n0) {
                     const int j = select_tp(m0, (int)pick);
-                    apply_flip(i, j, X, 0);
+                    apply_flip(i, j, X, 0, zfi, zfj);
                     fi = i;
                     fj = j;
                     return true;
@@ -435,7 +495,7 @@ struct Walker {
                 pick -= (uint32_t)n0;
                 if (pick < (uint32_t)n1) {
                     const int j = select_tp(m1, (int)pick);
-                    apply_flip(i, j, X, 1);
+                    apply_flip(i, j, X, 1, zfi, zfj);
                     fi = i;
                     fj = j;
                     return true;
@@ -491,7 +551,7 @@ struct Walker {
                 }
                 packed = from_lane(packed, win);
                 const int pi = packed & 0xFF, pj = (packed >> 8) & 0xFF;
-                apply_flip(pi, pj, (packed >> 16) & 3, (packed >> 18) & 1);
+                apply_flip(pi, pj, (packed >> 16) & 3, (packed >> 18) & 1, zfi, zfj);
                 fi = pi;
                 fj = pj;
                 return true;
@@ -516,68 +576,106 @@ struct Walker {
         return -1;
     }
 
-    // first term k (ascending, k != tt_i) that merges with term tt_i, or -1
-    __device__ int find_merge(int tt_i, const TV<T> (&tt)[3]) const
+    // two or more shared factors (w up to sign): the precondition of a merge
+    __device__ __forceinline__ static bool shares_two(const TV<T> (&tt)[3], const TV<T> (&tk)[3])
     {
-        int k = -1;
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            bool ok = false;
-            if (q * G < r) {
-                const int kk = q * G + gl;
-                if (kk < r && kk != tt_i) {
-                    const TV<T> tk[3] = {ld(kk, 0), ld(kk, 1), ld(kk, 2)};
-                    TV<T> o;
-                    ok = merge_kind(tt, tk, o) >= 0;
-                }
-            }
-            const uint64_t mk = gballot(ok);
-            if (k < 0 && mk) k = q * G + __builtin_ctzll(mk);
-        }
-        return k;
+        const bool eu = eqv(tt[0], tk[0]), ev = eqv(tt[1], tk[1]);
+        const bool ew = tk[2].d == tt[2].d &&
+                        (tk[2].s == tt[2].s || (!Z2 && tk[2].s == (tt[2].s ^ tt[2].d)));
+        return (eu && ev) || (eu && ew) || (ev && ew);
     }
 
-    // reduce the terms modified by the flip, cascading; returns merges
+    // First term k (ascending) that merges with term ia (k != ia) and with
+    // term ib (k != ib), in one pass over the terms; -1 where there is none
+    // or the tracked index is -1.  The slot loop has a wave-uniform bound, and
+    // the merge validity is evaluated only when some lane shares two factors.
+    __device__ void find_merges(int ia, const TV<T> (&ta)[3], int ib, const TV<T> (&tb)[3],
+                                int &ka, int &kb) const
+    {
+        ka = kb = -1;
+        const int qend = (a->cap + G - 1) / G;
+#pragma unroll 1
+        for (int q = 0; q < qend; ++q) {
+            const int kk = q * G + gl;
+            const bool live = kk < r;
+            TV<T> tk[3];
+            load_term(live ? kk : 0, tk);
+            bool oka = live && ia >= 0 && kk != ia && shares_two(ta, tk);
+            bool okb = live && ib >= 0 && kk != ib && shares_two(tb, tk);
+            if (__ballot(oka || okb)) {
+                TV<T> o;
+                oka = oka && merge_kind(ta, tk, o) >= 0;
+                okb = okb && merge_kind(tb, tk, o) >= 0;
+            }
+            const uint64_t ma = gballot(oka), mb = gballot(okb);
+            if (ka < 0 && ma) ka = q * G + __builtin_ctzll(ma);
+            if (kb < 0 && mb) kb = q * G + __builtin_ctzll(mb);
+        }
+    }
+
+    // merge term k into tracked term qq (Sec. 3.3.1 reduction); the merged
+    // term takes slot min(t,k) and slot max(t,k) is swap-removed; a merged
+    // factor of zero removes both terms.
+    __device__ void merge_into(int qq, int k, int &tr0, int &tr1)
+    {
+        const int tt_i = qq == 0 ? tr0 : tr1;
+        TV<T> tt[3], tk[3];
+        load_term(tt_i, tt);
+        load_term(k, tk);
+        TV<T> md;
+        const int kind = merge_kind(tt, tk, md);
+        const int lo = tt_i < k ? tt_i : k, hi = tt_i < k ? k : tt_i;
+        // the partner is consumed
+        if (qq == 0 && tr1 == k) tr1 = -1;
+        if (qq == 1 && tr0 == k) tr0 = -1;
+        if (md.d == 0) {
+            if (qq == 0)
+                tr0 = -1;
+            else
+                tr1 = -1;
+            swap_remove(hi, tr0, tr1);
+            swap_remove(lo, tr0, tr1);
+            return;
+        }
+        TV<T> nt[3] = {kind == 0 ? md : tt[0], kind == 1 ? md : tt[1], kind == 2 ? md : tt[2]};
+        normalise_regs(nt);
+        store_term(lo, nt);
+        wave_lds_sync();
+        if (qq == 0)
+            tr0 = lo;
+        else
+            tr1 = lo;
+        swap_remove(hi, tr0, tr1);
+    }
+
+    // Reduce the two terms modified by the flip, cascading: the first tracked
+    // term merges until it has no partner left, then the second.  Both are
+    // looked up in one pass; the second term's result of a pass is used once
+    // the first one is finished (nothing changed in between).  Returns merges.
     __device__ int reduce(int &tr0, int &tr1)
     {
         int merges = 0;
-        for (int qq = 0; qq < 2; ++qq) {
-            for (;;) {
-                const int tt_i = qq == 0 ? tr0 : tr1;
-                if (tt_i < 0) break;
-                TV<T> tt[3] = {ld(tt_i, 0), ld(tt_i, 1), ld(tt_i, 2)};
-                const int k = find_merge(tt_i, tt);
-                if (k < 0) break;
-                ++merges;
-                TV<T> tk[3] = {ld(k, 0), ld(k, 1), ld(k, 2)};
-                TV<T> md;
-                const int kind = merge_kind(tt, tk, md);
-                const int lo = tt_i < k ? tt_i : k, hi = tt_i < k ? k : tt_i;
-                // the partner is consumed
-                if (qq == 0 && tr1 == k) tr1 = -1;
-                if (qq == 1 && tr0 == k) tr0 = -1;
-                if (md.d == 0) {
-                    if (qq == 0)
-                        tr0 = -1;
-                    else
-                        tr1 = -1;
-                    swap_remove(hi, tr0, tr1);
-                    swap_remove(lo, tr0, tr1);
-                    break;
+        bool done0 = tr0 < 0;
+        for (;;) {
+            const int ia = done0 ? -1 : tr0, ib = tr1;
+            if (ia < 0 && ib < 0) break;
+            TV<T> ta[3] = {}, tb[3] = {};
+            if (ia >= 0) load_term(ia, ta);
+            if (ib >= 0) load_term(ib, tb);
+            int ka, kb;
+            find_merges(ia, ta, ib, tb, ka, kb);
+            if (!done0) {
+                if (ka >= 0) {
+                    ++merges;
+                    merge_into(0, ka, tr0, tr1);
+                    if (tr0 < 0) done0 = true;
+                    continue;
                 }
-                TV<T> nt[3] = {kind == 0 ? md : tt[0], kind == 1 ? md : tt[1],
-                               kind == 2 ? md : tt[2]};
-                normalise_regs(nt);
-                st(lo, 0, nt[0]);
-                st(lo, 1, nt[1]);
-                st(lo, 2, nt[2]);
-                wave_lds_sync();
-                if (qq == 0)
-                    tr0 = lo;
-                else
-                    tr1 = lo;
-                swap_remove(hi, tr0, tr1);
+                done0 = true;
             }
+            if (ib < 0 || kb < 0) break;
+            ++merges;
+            merge_into(1, kb, tr0, tr1);
         }
         return merges;
     }
@@ -681,7 +779,7 @@ struct Walker {
         }
         cnt[C_FLIPS]++;
         int tr0 = fi, tr1 = fj;
-        const bool zi = has_zero(fi), zj = has_zero(fj);
+        const bool zi = zfi, zj = zfj;
         if (zi && zj) {
             swap_remove(fi > fj ? fi : fj, tr0, tr1);
             swap_remove(fi > fj ? fj : fi, tr0, tr1);
