@@ -556,67 +556,70 @@ static int partner(const or_scheme *s, int i, int j, int X, int role, int *sigma
     return 1;
 }
 
+/* Candidates of the attempt (i, X): the valid (j, role), role 0 then 1, j
+ * ascending.  Returns their number; when pick >= 0, the pick-th candidate is
+ * written to *pj, *psg, *prole. */
+static int attempt_candidates(const or_scheme *s, int i, int X, long pick, int *pj, int *psg,
+                              int *prole)
+{
+    int n = 0;
+    for (int role = 0; role < 2; ++role)
+        for (int j = 0; j < s->r; ++j) {
+            int sg;
+            if (!partner(s, i, j, X, role, &sg)) continue;
+            if (n == pick) {
+                *pj = j; *psg = sg; *prole = role;
+            }
+            ++n;
+        }
+    return n;
+}
+
 /* try_flip of Algorithm 1.  Reading (the paper does not fix how a flip is
  * sampled): attempt a = 0..flip_tries-1 draws block (t,a,0): term
  * i = U(w0, r), factor X = U(w1, 3); its candidates are the valid
  * (j, role) in order role 0 then 1, j ascending; a non-empty list yields
- * candidate U(w2, |list|).  If every attempt is empty, all valid (i, X,
- * role, j) in that nesting order are enumerated and entry U(w0, count) of
- * block (t, flip_tries, 0) is taken.  Only when no valid flip exists at all
- * does try_flip fail.  On success *pi and *pj hold the modified terms. */
+ * candidate U(w2, |list|).  If every attempt is empty, block (t, flip_tries, 0)
+ * gives a starting pair p0 = U(w0, 3r); the pairs p = 3i + X are visited
+ * cyclically from p0 and the first one with candidates yields candidate
+ * U(w1, |list|).  Only when no pair has a candidate (no valid flip exists at
+ * all) does try_flip fail.  On success *pi and *pj hold the modified terms. */
 static int try_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *pj)
 {
     or_scheme *s = &w->cur;
     int r = s->r;
     uint32_t rw[4];
+    int j = -1, sg = 0, role = 0;
     if (r < 2) return 0;
     for (int a = 0; a < prm->flip_tries; ++a) {
         draw(prm->seed, t, (uint32_t)a, 0, rw);
         w->c.attempts++;
         int i = uniform_below(rw[0], r);
         int X = uniform_below(rw[1], 3);
-        int cj[2 * OR_MAXT], cs[2 * OR_MAXT], cr[2 * OR_MAXT];
-        int nc = 0;
-        for (int role = 0; role < 2; ++role)
-            for (int j = 0; j < r; ++j) {
-                int sg;
-                if (partner(s, i, j, X, role, &sg)) {
-                    cj[nc] = j; cs[nc] = sg; cr[nc] = role; ++nc;
-                }
-            }
-        if (nc > 0) {
-            int c = uniform_below(rw[2], nc);
-            or_flip(s, i, cj[c], X, cs[c], cr[c]);
-            *pi = i; *pj = cj[c];
+        int n = attempt_candidates(s, i, X, -1, &j, &sg, &role);
+        if (n > 0) {
+            attempt_candidates(s, i, X, uniform_below(rw[2], n), &j, &sg, &role);
+            or_flip(s, i, j, X, sg, role);
+            *pi = i; *pj = j;
             return 1;
         }
     }
-    /* exhaustive fallback */
+    /* every attempt was empty: cyclic search over the (i, X) pairs */
     w->c.fallbacks++;
-    long count = 0;
-    for (int i = 0; i < r; ++i)
-        for (int X = 0; X < 3; ++X)
-            for (int role = 0; role < 2; ++role)
-                for (int j = 0; j < r; ++j) {
-                    int sg;
-                    if (partner(s, i, j, X, role, &sg)) ++count;
-                }
-    if (count == 0) return 0;
     draw(prm->seed, t, (uint32_t)prm->flip_tries, 0, rw);
-    long pick = uniform_below(rw[0], (int)count);
-    for (int i = 0; i < r; ++i)
-        for (int X = 0; X < 3; ++X)
-            for (int role = 0; role < 2; ++role)
-                for (int j = 0; j < r; ++j) {
-                    int sg;
-                    if (!partner(s, i, j, X, role, &sg)) continue;
-                    if (pick-- == 0) {
-                        or_flip(s, i, j, X, sg, role);
-                        *pi = i; *pj = j;
-                        return 1;
-                    }
-                }
-    return 0; /* unreachable */
+    int npairs = 3 * r;
+    int p0 = uniform_below(rw[0], npairs);
+    for (int q = 0; q < npairs; ++q) {
+        int p = (p0 + q) % npairs;
+        int i = p / 3, X = p % 3;
+        int n = attempt_candidates(s, i, X, -1, &j, &sg, &role);
+        if (n == 0) continue;
+        attempt_candidates(s, i, X, uniform_below(rw[1], n), &j, &sg, &role);
+        or_flip(s, i, j, X, sg, role);
+        *pi = i; *pj = j;
+        return 1;
+    }
+    return 0;
 }
 
 /* expand of Algorithm 1 (plus or split, 50/50, Sec. 3.3.1).  Reading: up to

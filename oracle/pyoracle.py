@@ -180,7 +180,7 @@ def copy(s: Scheme) -> Scheme:
 
 
 def make_params(seed=0, max_iters=100000, plateau=20000, target_rank=0, r_cap=None,
-                flip_tries=8, restart_from_best=0, t_eq=42949673, t_reduce=1 << 32,
+                flip_tries=7, restart_from_best=0, t_eq=42949673, t_reduce=1 << 32,
                 t_expand=0, r0=None):
     if r_cap is None:
         r_cap = (r0 or 0) + 8

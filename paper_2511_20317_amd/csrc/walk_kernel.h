@@ -466,87 +466,63 @@ struct Walker {
         }
     }
 
-    // Exhaustive search when every attempt failed: all valid (i, X, role, j)
-    // in that nesting order, entry U(w0, count) of block (t, flip_tries, 0).
+    // When every attempt failed: block (t, flip_tries, 0) gives a starting
+    // pair p0 = U(w0, 3r); the pairs p = 3i + X are visited cyclically from p0
+    // and the first pair with a valid partner yields candidate U(w1, n).
+    // None at all: a dead end.
     __device__ bool fallback_tp(int &fi, int &fj)
     {
         cnt[C_FALLBACKS]++;
         uint64_t m0[S], m1[S];
         int n0, n1;
-        uint32_t total = 0;
-        for (int i = 0; i < r; ++i)
-            for (int X = 0; X < 3; ++X) {
-                candidates_tp(i, X, m0, m1, n0, n1);
-                total += (uint32_t)(n0 + n1);
-            }
-        if (total == 0) return false;
         const Philox4 w = walk_block(seed, t, (uint32_t)a->flip_tries, 0);
-        uint32_t pick = below(w.x[0], total);
-        for (int i = 0; i < r; ++i)
-            for (int X = 0; X < 3; ++X) {
-                candidates_tp(i, X, m0, m1, n0, n1);
-                if (pick < (uint32_t)n0) {
-                    const int j = select_tp(m0, (int)pick);
-                    apply_flip(i, j, X, 0, zfi, zfj);
-                    fi = i;
-                    fj = j;
-                    return true;
-                }
-                pick -= (uint32_t)n0;
-                if (pick < (uint32_t)n1) {
-                    const int j = select_tp(m1, (int)pick);
-                    apply_flip(i, j, X, 1, zfi, zfj);
-                    fi = i;
-                    fj = j;
-                    return true;
-                }
-                pick -= (uint32_t)n1;
-            }
-        return false;  // not reached: total counted every candidate
+        const int npairs = 3 * r;
+        const int p0 = (int)below(w.x[0], (uint32_t)npairs);
+        for (int q = 0; q < npairs; ++q) {
+            int p = p0 + q;
+            if (p >= npairs) p -= npairs;
+            const int i = p / 3, X = p - 3 * i;
+            candidates_tp(i, X, m0, m1, n0, n1);
+            const int n = n0 + n1;
+            if (n == 0) continue;
+            int c = (int)below(w.x[1], (uint32_t)n);
+            const int role = c >= n0;
+            if (role) c -= n0;
+            const int j = role ? select_tp(m1, c) : select_tp(m0, c);
+            apply_flip(i, j, X, role, zfi, zfj);
+            fi = i;
+            fj = j;
+            return true;
+        }
+        return false;
     }
 
-    // The same search with the (i, X) pairs p = 3i + X spread over the lanes:
-    // pair p is handled by lane p mod G in round p / G.
+    // The same search with G consecutive pairs per round, one per lane; the
+    // first lane (in pair order) with a partner wins.
     __device__ bool fallback_ap(int &fi, int &fj)
     {
         cnt[C_FALLBACKS]++;
-        const int npairs = 3 * r;
-        uint32_t total = 0;
-        for (int p0 = 0; p0 < npairs; p0 += G) {
-            const int p = p0 + gl;
-            uint64_t m0 = 0, m1 = 0;
-            if (p < npairs) candidates_ap(p / 3, p % 3, m0, m1);
-            uint32_t c = (uint32_t)(popc64(m0) + popc64(m1));
-            // group sum
-            for (int off = 1; off < G; off <<= 1) c += (uint32_t)__shfl_xor((int)c, off, G);
-            total += c;
-        }
-        if (total == 0) return false;
         const Philox4 w = walk_block(seed, t, (uint32_t)a->flip_tries, 0);
-        uint32_t pick = below(w.x[0], total);
-        for (int p0 = 0; p0 < npairs; p0 += G) {
-            const int p = p0 + gl;
+        const int npairs = 3 * r;
+        const int p0 = (int)below(w.x[0], (uint32_t)npairs);
+        for (int base = 0; base < npairs; base += G) {
+            const int q = base + gl;
+            int p = p0 + q;
+            if (p >= npairs) p -= npairs;
+            const int i = p / 3, X = p - 3 * i;
             uint64_t m0 = 0, m1 = 0;
-            if (p < npairs) candidates_ap(p / 3, p % 3, m0, m1);
-            const uint32_t c = (uint32_t)(popc64(m0) + popc64(m1));
-            // inclusive scan over the lanes of the group
-            uint32_t incl = c;
-            for (int off = 1; off < G; off <<= 1) {
-                const uint32_t v = (uint32_t)__shfl_up((int)incl, off, G);
-                if (gl >= off) incl += v;
-            }
-            const uint32_t round_total = from_lane(incl, G - 1);
-            if (pick < round_total) {
-                const bool mine = pick < incl && pick >= incl - c;
-                const int win = __builtin_ctzll(gballot(mine));
+            if (q < npairs) candidates_ap(i, X, m0, m1);
+            const int n0 = popc64(m0), n = n0 + popc64(m1);
+            const uint64_t ok = gballot(n > 0);
+            if (ok) {
+                const int win = __builtin_ctzll(ok);
                 uint32_t packed = 0;
                 if (gl == win) {
-                    int cc = (int)(pick - (incl - c));
-                    const int n0 = popc64(m0);
-                    const int role = cc >= n0;
-                    if (role) cc -= n0;
-                    const int j = kth_bit(role ? m1 : m0, cc);
-                    packed = (uint32_t)(p / 3) | ((uint32_t)j << 8) | ((uint32_t)(p % 3) << 16) |
+                    int c = (int)below(w.x[1], (uint32_t)n);
+                    const int role = c >= n0;
+                    if (role) c -= n0;
+                    const int j = kth_bit(role ? m1 : m0, c);
+                    packed = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)X << 16) |
                              ((uint32_t)role << 18);
                 }
                 packed = from_lane(packed, win);
@@ -556,9 +532,8 @@ struct Walker {
                 fj = pj;
                 return true;
             }
-            pick -= round_total;
         }
-        return false;  // not reached
+        return false;
     }
 
     // ------------------------------------------------------------------ reduce
@@ -731,20 +706,20 @@ struct Walker {
     }
 
     // ------------------------------------------------------------------ HBM
+    // HBM holds terms as 6 consecutive uint64 (u.d u.s v.d v.s w.d w.s); lane
+    // l of the group moves terms l, l+G, ...
     __device__ void load_scheme(const uint64_t *src, int rr)
     {
-        for (int e = gl; e < rr * 6; e += G) {
-            const int k = e / 6, x = e % 6;
-            lds[idx(k, x >> 1) + (x & 1)] = (T)src[e];
-        }
+        for (int k = gl; k < rr; k += G)
+#pragma unroll
+            for (int x = 0; x < 6; ++x) lds[idx(k, x >> 1) + (x & 1)] = (T)src[k * 6 + x];
         wave_lds_sync();
     }
     __device__ void store_scheme(uint64_t *dst) const
     {
-        for (int e = gl; e < r * 6; e += G) {
-            const int k = e / 6, x = e % 6;
-            dst[e] = (uint64_t)lds[idx(k, x >> 1) + (x & 1)];
-        }
+        for (int k = gl; k < r; k += G)
+#pragma unroll
+            for (int x = 0; x < 6; ++x) dst[k * 6 + x] = (uint64_t)lds[idx(k, x >> 1) + (x & 1)];
     }
 
     __device__ void restart_check()

@@ -233,7 +233,7 @@ def unpack(packed, m, n, p, rank, mode=TSF_TERNARY) -> Scheme:
 # ---------------------------------------------------------------------------
 # walks on the GPU
 # ---------------------------------------------------------------------------
-def walk_params(base_seed=0, first_walk_id=0, max_iters=100000, plateau=20000, flip_tries=8,
+def walk_params(base_seed=0, first_walk_id=0, max_iters=100000, plateau=20000, flip_tries=7,
                 restart_from_best=0, t_eq=EQ_ACCEPT, t_reduce=ALWAYS, t_expand=0):
     return WalkParams(base_seed, first_walk_id, max_iters, plateau, flip_tries,
                       restart_from_best, t_eq, t_reduce, t_expand)
