@@ -29,9 +29,11 @@ PEAK_HBM = 8.0e12
 def ops_per_iteration(cnt, iters, mean_rank, wd=1):
     """Algorithmic 32-bit integer operations of one walk iteration, from the
     walk's own counters (model stated in the design doc):
-      Philox block          100 ops (10 rounds x (4 mul + 4 xor + 2 add))
-      partner scan          (4*wd + 2) ops per term per attempt
-      full search           2 passes x 3 kinds x r terms x r partners x (4*wd + 2)
+      Philox block          100 ops (10 rounds x (4 mul + 4 xor + 2 add)), one per
+                            attempt drawn, per cyclic search, per gate, per expand try
+      partner scan          (4*wd + 2) ops per term per attempt, 12*wd per attempt
+                            for the validity of the (about one) matching term
+      cyclic search         3 pair scans of r terms x (4*wd + 2)
       flip + normalisation  30*wd
       reduction scan        2 modified terms x r x (7*wd + 2)
       bookkeeping           20
@@ -39,14 +41,14 @@ def ops_per_iteration(cnt, iters, mean_rank, wd=1):
     r = mean_rank
     a = cnt["attempts"] / iters
     fb = cnt["fallbacks"] / iters
-    gate = 1.0
     exp_blocks = (cnt["expands"] + 8 * cnt["expand_fails"]) / iters
-    philox = 100.0 * (a + fb + gate + exp_blocks)
-    scan = a * r * (4 * wd + 2)
-    full = fb * 2 * 3 * r * r * (4 * wd + 2)
-    apply = 30.0 * wd * cnt["flips"] / iters
-    red = 2 * r * (7 * wd + 2) * cnt["flips"] / iters
-    return philox + scan + full + apply + red + 20.0
+    flips = cnt["flips"] / iters
+    philox = 100.0 * (a + fb + 1.0 + exp_blocks)
+    scan = a * (r * (4 * wd + 2) + 12 * wd)
+    cyclic = fb * 3 * r * (4 * wd + 2)
+    apply = 30.0 * wd * flips
+    red = 2 * r * (7 * wd + 2) * flips
+    return philox + scan + cyclic + apply + red + 20.0
 
 
 def cpu_baseline(n_walks=256, iters=100000, threads=None):
@@ -81,6 +83,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-walks", type=int, default=256)
     ap.add_argument("--cpu-iters", type=int, default=100000)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (HBM counter scale)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the walks shard by walk id with no "
@@ -129,6 +133,15 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if args.calibrate_copy_mib:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE read the
+        # scale of those counters
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     hdr = batch.headers()
     kernel_ms = [a.elapsed_time(b) for a, b in ev]
