@@ -238,6 +238,55 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
 tsf_status tsf_verify_batch(const tsf_walk_batch *b, int32_t which, int64_t *n_violated,
                             void *hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Learned flip proposal: a scoring network run on the MFMA matrix cores     */
+/* ------------------------------------------------------------------------ */
+
+/* Not in the paper (its Sec. 5.4 names learned search as future work): a
+ * multilayer perceptron that scores candidate flips so that a walk can try the
+ * best-scored one first.  With X an M x 512 bf16 feature matrix:
+ *   z1 = X W1 + b1, h1 = bf16(relu(z1)); z2 = h1 W2 + b2, h2 = bf16(relu(z2));
+ *   logit = h2 . w3 + b3;  loss = mean(softplus(logit) - y logit).
+ * bf16 operands, fp32 accumulation (MFMA).  Parameters are fp32 masters in one
+ * vector: W1^T (256 x 512, row n = column n of W1), b1 (256), W2^T (256 x 256),
+ * b2 (256), w3 (256), b3 (1, padded to 4).  bf16 compute copies: W1^T, W2^T,
+ * W2 (256 x 256, for the backward pass) and w3. */
+#define TSF_MLP_IN 512
+#define TSF_MLP_HID 256
+#define TSF_MLP_NPARAM 197380
+#define TSF_MLP_NBF16 262400
+
+typedef struct {
+    float *param;      /* device, TSF_MLP_NPARAM fp32 masters                    */
+    float *grad;       /* device, TSF_MLP_NPARAM (written by tsf_mlp_bwd)       */
+    float *adam_m;     /* device, TSF_MLP_NPARAM Adam first moments             */
+    float *adam_v;     /* device, TSF_MLP_NPARAM Adam second moments            */
+    uint16_t *wbf;     /* device, TSF_MLP_NBF16 bf16 compute copies            */
+} tsf_mlp;
+
+/* Refresh the bf16 compute copies from the fp32 masters.  Async on the stream. */
+tsf_status tsf_mlp_sync(const tsf_mlp *net, void *hip_stream);
+
+/* Forward pass of M rows: X (device, M x 512 bf16, row-major) -> h1, h2
+ * (device, M x 256 bf16 each, caller workspace) and logit (device, M fp32).
+ * Async on the stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
+tsf_status tsf_mlp_fwd(const tsf_mlp *net, const uint16_t *X, int32_t M, uint16_t *h1,
+                       uint16_t *h2, float *logit, void *hip_stream);
+
+/* Backward pass of the mean binary cross-entropy against labels y (device, M
+ * fp32 in {0,1}), using the forward's h1, h2, logit: writes every gradient into
+ * net->grad (overwriting it) and the loss into *loss (device fp32).  d2, d1
+ * (device, M x 256 bf16) and d3 (device, M fp32) are caller workspace.
+ * Async on the stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
+tsf_status tsf_mlp_bwd(const tsf_mlp *net, const uint16_t *X, const float *y, int32_t M,
+                       const uint16_t *h1, const uint16_t *h2, const float *logit, uint16_t *d2,
+                       uint16_t *d1, float *d3, float *loss, void *hip_stream);
+
+/* One Adam step (Kingma & Ba 2015; step = 1, 2, ... for the bias correction)
+ * on the fp32 masters from net->grad, then tsf_mlp_sync.  Async on the stream. */
+tsf_status tsf_mlp_step(const tsf_mlp *net, float lr, float beta1, float beta2, float eps,
+                        int32_t step, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

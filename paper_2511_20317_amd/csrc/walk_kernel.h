@@ -112,6 +112,18 @@ struct Walker {
     Philox4 pb;
     // zero-factor flags of the two terms of the last flip
     bool zfi, zfj;
+    // largest rank of the walks of this wavefront, rounded up to even: the
+    // wave-uniform bound of the attempt-parallel match scan
+    int scan_end;
+
+    __device__ __forceinline__ void update_scan_end()
+    {
+        int m = 0;
+#pragma unroll
+        for (int g = 0; g < 64 / G; ++g) m = max(m, __builtin_amdgcn_readlane(r, g * G));
+        m = min(m, a->cap2);
+        scan_end = (m + 1) & ~1;
+    }
 
     __device__ __forceinline__ uint64_t gballot(bool p) const
     {
@@ -358,7 +370,7 @@ struct Walker {
         const TV<T> xi = ld(i, X);
         const T nsi = (!Z2 && X == 2) ? (xi.s ^ xi.d) : xi.s;  // accepted signs besides xi.s
         const T *col = lds + idx(0, X);
-        const int kend = a->cap2;  // even, uniform
+        const int kend = scan_end;  // even, wave-uniform
         uint32_t lo = 0, hi = 0;
         int k = 0;
         for (; k < kend && k < 32; k += 2) {
@@ -397,6 +409,7 @@ struct Walker {
         if (r < 2) return false;
         const int T_ = a->flip_tries;
         if constexpr (AP) {
+            update_scan_end();
             constexpr int P = G - 1;  // attempts per batch
             for (int base = 0; base < T_; base += P) {
                 const int att = base + gl;

@@ -61,6 +61,14 @@ class Launch(C.Structure):
                 ("strategy", C.c_int32)]
 
 
+class MlpC(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("adam_m", C.c_void_p),
+                ("adam_v", C.c_void_p), ("wbf", C.c_void_p)]
+
+
+MLP_IN, MLP_HID, MLP_NPARAM, MLP_NBF16 = 512, 256, 197380, 262400
+
+
 # numpy view of tsf_walk_header (160 bytes)
 HEADER_DTYPE = np.dtype([("m", "<i4"), ("n", "<i4"), ("p", "<i4"), ("mode", "<i4"),
                          ("r_cap", "<i4"), ("target_rank", "<i4"), ("rank", "<i4"),
@@ -97,6 +105,14 @@ def lib():
             ("tsf_walk", [C.c_void_p, P(WalkParams), P(WalkBatchC), C.c_int64, P(Launch),
                           C.c_void_p]),
             ("tsf_verify_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p]),
+            ("tsf_mlp_sync", [P(MlpC), C.c_void_p]),
+            ("tsf_mlp_fwd", [P(MlpC), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p]),
+            ("tsf_mlp_bwd", [P(MlpC), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p]),
+            ("tsf_mlp_step", [P(MlpC), C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
+                              C.c_void_p]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -337,3 +353,97 @@ class WalkBatch:
     def counters(self, walk, headers=None):
         h = (headers if headers is not None else self.headers())[walk]
         return {name: int(h["counters"][k]) for k, name in enumerate(COUNTER_NAMES)}
+
+
+# ---------------------------------------------------------------------------
+# learned proposal network
+# ---------------------------------------------------------------------------
+class Mlp:
+    """Device buffers of the proposal network (see tsf.h)."""
+
+    def __init__(self, device="cuda"):
+        import torch
+        self.torch = torch
+        dev = torch.device(device)
+        self.param = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=dev)
+        self.grad = torch.zeros_like(self.param)
+        self.adam_m = torch.zeros_like(self.param)
+        self.adam_v = torch.zeros_like(self.param)
+        self.wbf = torch.zeros(MLP_NBF16, dtype=torch.int16, device=dev)
+        self.step_count = 0
+
+    def c(self):
+        return MlpC(self.param.data_ptr(), self.grad.data_ptr(), self.adam_m.data_ptr(),
+                    self.adam_v.data_ptr(), self.wbf.data_ptr())
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def set_params(self, W1, b1, W2, b2, w3, b3):
+        """From the math layout (W1: 512 x 256, W2: 256 x 256) to the packed vector."""
+        v = np.concatenate([np.asarray(W1, np.float32).T.reshape(-1), np.asarray(b1, np.float32),
+                            np.asarray(W2, np.float32).T.reshape(-1), np.asarray(b2, np.float32),
+                            np.asarray(w3, np.float32), np.asarray(b3, np.float32).reshape(-1)[:1],
+                            np.zeros(3, np.float32)])
+        assert v.size == MLP_NPARAM
+        self.param.copy_(self.torch.from_numpy(v))
+        self.sync()
+
+    def unpack(self, vec):
+        """packed fp32 vector -> dict in the math layout"""
+        v = np.asarray(vec, dtype=np.float64)
+        H, I = MLP_HID, MLP_IN
+        o = 0
+        W1 = v[o:o + H * I].reshape(H, I).T; o += H * I
+        b1 = v[o:o + H]; o += H
+        W2 = v[o:o + H * H].reshape(H, H).T; o += H * H
+        b2 = v[o:o + H]; o += H
+        w3 = v[o:o + H]; o += H
+        b3 = v[o:o + 1]
+        return {"W1": W1, "b1": b1, "W2": W2, "b2": b2, "w3": w3, "b3": b3}
+
+    def sync(self):
+        check(lib().tsf_mlp_sync(C.byref(self.c()), self._stream()))
+
+    def forward(self, X, h1=None, h2=None, logit=None):
+        torch = self.torch
+        M = X.shape[0]
+        h1 = h1 if h1 is not None else torch.empty((M, MLP_HID), dtype=torch.int16, device=X.device)
+        h2 = h2 if h2 is not None else torch.empty_like(h1)
+        logit = logit if logit is not None else torch.empty(M, dtype=torch.float32, device=X.device)
+        check(lib().tsf_mlp_fwd(C.byref(self.c()), C.c_void_p(X.data_ptr()), M,
+                                C.c_void_p(h1.data_ptr()), C.c_void_p(h2.data_ptr()),
+                                C.c_void_p(logit.data_ptr()), self._stream()))
+        return h1, h2, logit
+
+    def backward(self, X, y, h1, h2, logit):
+        torch = self.torch
+        M = X.shape[0]
+        d2 = torch.empty((M, MLP_HID), dtype=torch.int16, device=X.device)
+        d1 = torch.empty_like(d2)
+        d3 = torch.empty(M, dtype=torch.float32, device=X.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+        check(lib().tsf_mlp_bwd(C.byref(self.c()), C.c_void_p(X.data_ptr()),
+                                C.c_void_p(y.data_ptr()), M, C.c_void_p(h1.data_ptr()),
+                                C.c_void_p(h2.data_ptr()), C.c_void_p(logit.data_ptr()),
+                                C.c_void_p(d2.data_ptr()), C.c_void_p(d1.data_ptr()),
+                                C.c_void_p(d3.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                self._stream()))
+        return loss
+
+    def step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        check(lib().tsf_mlp_step(C.byref(self.c()), lr, beta1, beta2, eps, self.step_count,
+                                 self._stream()))
+
+
+def bf16_bits(a):
+    """float array -> int16 array of bf16 bits (round to nearest even)"""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return r.view(np.int16)
+
+
+def bf16_to_float(bits):
+    b = np.asarray(bits).view(np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32).astype(np.float64)
