@@ -172,6 +172,26 @@ typedef struct {
     int32_t reserved;
 } tsf_record;
 
+/* One logged walk iteration (128 bytes), for training the proposal network:
+ * the flip applied at iteration `iter`, as the six factors of its two terms
+ * before the flip in role order (x_i, y_i, z_i, x_j, y_j, z_j: x the shared
+ * kind, y the kind that was added to, z the kind that was subtracted from),
+ * each as a (digits, signs) pair, and the rank before and after the whole
+ * iteration.  rank_before = -1 marks an iteration without a flip. */
+typedef struct {
+    int64_t iter;
+    int32_t rank_before;
+    int32_t rank_after;
+    int32_t format_slot;       /* tsf_format_slot of the walk's format          */
+    int32_t reserved;
+    uint64_t f[12];
+    uint64_t pad;
+} tsf_flip_log;
+
+/* Slot of a format in the proposal network's one-hot (0..14 for fifteen small
+ * formats, independent of the order of m, n, p; 15 for any other). */
+int32_t tsf_format_slot(int32_t m, int32_t n, int32_t p);
+
 /* A batch of walks.  All buffers are device memory owned by the caller.
  * Walk w uses:  hdr[w];  cur, best, start: packed schemes of `capacity` terms
  * at offset w * capacity * 6 uint64;  rec: rec_cap records at w * rec_cap.
@@ -191,6 +211,11 @@ typedef struct {
     uint64_t *best;
     const uint64_t *start;
     tsf_record *rec;
+    tsf_flip_log *log;         /* optional (NULL = off): log_cap records per walk;
+                                  iteration t of walk w goes to w*log_cap + t-1
+                                  while t <= log_cap (uniform proposals only)      */
+    int32_t log_cap;
+    int32_t reserved2;
 } tsf_walk_batch;
 
 /* Launch configuration.  strategy: 1 = attempt-parallel (each lane of a walk
@@ -238,6 +263,13 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
 tsf_status tsf_verify_batch(const tsf_walk_batch *b, int32_t which, int64_t *n_violated,
                             void *hip_stream);
 
+/* Expand n log records into bf16 feature rows X (device, n x 512) of the
+ * proposal network: entries 0..383 the six factors (64 entries each, +-1/0),
+ * 384 + format_slot one-hot, 400 + min(rank_before, 95) one-hot, the rest 0.
+ * Async on the stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
+tsf_status tsf_features_from_log(const tsf_flip_log *log, int64_t n, uint16_t *X,
+                                 void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Learned flip proposal: a scoring network run on the MFMA matrix cores     */
 /* ------------------------------------------------------------------------ */
@@ -281,6 +313,35 @@ tsf_status tsf_mlp_fwd(const tsf_mlp *net, const uint16_t *X, int32_t M, uint16_
 tsf_status tsf_mlp_bwd(const tsf_mlp *net, const uint16_t *X, const float *y, int32_t M,
                        const uint16_t *h1, const uint16_t *h2, const float *logit, uint16_t *d2,
                        uint16_t *d1, float *d3, float *loss, void *hip_stream);
+
+/* Walks with the learned proposal.  Each iteration: the first K = flip_tries
+ * random attempts (K <= lanes_per_walk - 1, attempt-parallel strategy) each
+ * yield their candidate flip exactly as with uniform proposals; the network
+ * scores the K candidates (rows of the same feature layout as
+ * tsf_features_from_log) and the walk applies the highest-scored one (ties:
+ * the lower attempt).  If no attempt has a candidate the uniform fallback
+ * search runs.  Everything else in the iteration is unchanged, so every scheme
+ * is exact and verified as before.  The attempts counter grows by K per
+ * iteration.  Workspace (device, caller-owned), R = 8 * n_walks rows:
+ * cand R uint32, feat R x 512 bf16, h1 and h2 R x 256 bf16, logit R fp32.
+ * choice (optional, device): choice_cap bytes per walk; the attempt applied at
+ * iteration t (255 = fallback) goes to w*choice_cap + t-1 while t <= choice_cap.
+ * Runs n_iters iterations (each a propose kernel, the network, an apply
+ * kernel), asynchronous on `hip_stream`.  Errors: TSF_E_ARG, TSF_E_CAPACITY,
+ * TSF_E_DEVICE. */
+typedef struct {
+    uint32_t *cand;
+    uint16_t *feat;
+    uint16_t *h1, *h2;
+    float *logit;
+    uint8_t *choice;
+    int32_t choice_cap;
+    int32_t reserved;
+} tsf_learn_ws;
+
+tsf_status tsf_walk_learned(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                            const tsf_mlp *net, const tsf_learn_ws *ws, int64_t n_iters,
+                            const tsf_launch *launch, void *hip_stream);
 
 /* One Adam step (Kingma & Ba 2015; step = 1, 2, ... for the bias correction)
  * on the fp32 masters from net->grad, then tsf_mlp_sync.  Async on the stream. */

@@ -103,3 +103,31 @@ def adam(p, g, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         vh = v / (1 - b2 ** t)
         out[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
     return out
+
+
+# Slots of the format one-hot of the feature rows: fifteen small formats with
+# sorted dimensions, 15 for every other format (the same table as the
+# library's, written out here independently).
+FORMAT_SLOTS = {(2, 2, 2): 0, (2, 2, 3): 1, (2, 2, 4): 2, (2, 3, 3): 3, (2, 3, 4): 4,
+                (3, 3, 3): 5, (3, 3, 4): 6, (2, 4, 4): 7, (3, 4, 4): 8, (3, 3, 5): 9,
+                (4, 4, 4): 10, (3, 4, 5): 11, (4, 4, 5): 12, (4, 5, 5): 13, (5, 5, 5): 14}
+
+
+def format_slot(m, n, p):
+    return FORMAT_SLOTS.get(tuple(sorted((m, n, p))), 15)
+
+
+def feature_row(factors, slot, rank):
+    """factors: six int vectors (x_i, y_i, z_i, x_j, y_j, z_j) with entries in
+    {-1,0,1} (length <= 64) -> the 512 feature values (fp64)."""
+    row = np.zeros(D_IN)
+    for b, vec in enumerate(factors):
+        v = np.asarray(vec, dtype=np.float64)
+        row[64 * b:64 * b + v.size] = v
+    row[384 + slot] = 1.0
+    row[400 + min(max(rank, 0), 95)] = 1.0
+    return row
+
+
+def masks_to_vec(d, s, length=64):
+    return np.array([0 if not (d >> e) & 1 else (-1 if (s >> e) & 1 else 1) for e in range(length)])

@@ -575,6 +575,9 @@ static int attempt_candidates(const or_scheme *s, int i, int X, long pick, int *
     return n;
 }
 
+static int fallback_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *pj, int *pX,
+                         int *prole);
+
 /* try_flip of Algorithm 1.  Reading (the paper does not fix how a flip is
  * sampled): attempt a = 0..flip_tries-1 draws block (t,a,0): term
  * i = U(w0, r), factor X = U(w1, 3); its candidates are the valid
@@ -584,7 +587,8 @@ static int attempt_candidates(const or_scheme *s, int i, int X, long pick, int *
  * cyclically from p0 and the first one with candidates yields candidate
  * U(w1, |list|).  Only when no pair has a candidate (no valid flip exists at
  * all) does try_flip fail.  On success *pi and *pj hold the modified terms. */
-static int try_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *pj)
+static int try_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *pj, int *pX,
+                    int *prole)
 {
     or_scheme *s = &w->cur;
     int r = s->r;
@@ -599,12 +603,21 @@ static int try_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *p
         int n = attempt_candidates(s, i, X, -1, &j, &sg, &role);
         if (n > 0) {
             attempt_candidates(s, i, X, uniform_below(rw[2], n), &j, &sg, &role);
-            or_flip(s, i, j, X, sg, role);
-            *pi = i; *pj = j;
+            *pi = i; *pj = j; *pX = X; *prole = role;
             return 1;
         }
     }
-    /* every attempt was empty: cyclic search over the (i, X) pairs */
+    return fallback_flip(w, prm, t, pi, pj, pX, prole);
+}
+
+/* every attempt was empty: cyclic search over the (i, X) pairs */
+static int fallback_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *pj, int *pX,
+                         int *prole)
+{
+    or_scheme *s = &w->cur;
+    int r = s->r;
+    uint32_t rw[4];
+    int j = -1, sg = 0, role = 0;
     w->c.fallbacks++;
     draw(prm->seed, t, (uint32_t)prm->flip_tries, 0, rw);
     int npairs = 3 * r;
@@ -615,8 +628,7 @@ static int try_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *p
         int n = attempt_candidates(s, i, X, -1, &j, &sg, &role);
         if (n == 0) continue;
         attempt_candidates(s, i, X, uniform_below(rw[1], n), &j, &sg, &role);
-        or_flip(s, i, j, X, sg, role);
-        *pi = i; *pj = j;
+        *pi = i; *pj = j; *pX = X; *prole = role;
         return 1;
     }
     return 0;
@@ -657,18 +669,67 @@ static void restart_check(or_walk *w, const or_params *prm, int64_t t)
     }
 }
 
-static void one_iteration(or_walk *w, const or_params *prm, int64_t t)
+/* the two terms of a flip before it is applied, in role order, as masks */
+static void log_factors(const or_scheme *s, int i, int j, int X, int role, or_log *lg)
+{
+    int Y, Z;
+    other_kinds(X, role, &Y, &Z);
+    const int8_t *fac[6] = { s->f[X][i], s->f[Y][i], s->f[Z][i], s->f[X][j], s->f[Y][j], s->f[Z][j] };
+    const int kind[6] = { X, Y, Z, X, Y, Z };
+    for (int q = 0; q < 6; ++q) {
+        uint64_t d = 0, sg = 0;
+        for (int e = 0; e < or_len(s, kind[q]); ++e) {
+            if (fac[q][e] != 0) d |= 1ull << e;
+            if (fac[q][e] < 0) sg |= 1ull << e;
+        }
+        lg->f[2 * q] = d;
+        lg->f[2 * q + 1] = sg;
+    }
+}
+
+/* One iteration of Algorithm 1.  choice < 0: uniform proposals (try_flip);
+ * choice >= 0: the externally chosen attempt (255 = fallback), see
+ * or_walk_run_choices.  Returns 0, or 1 when the choice was inconsistent. */
+static int one_iteration(or_walk *w, const or_params *prm, int64_t t, int choice, or_log *lg)
 {
     or_scheme *s = &w->cur;
-    int i = -1, j = -1;
+    int i = -1, j = -1, X = 0, role = 0;
+    int found;
     w->c.iters++;
-    if (!try_flip(w, prm, t, &i, &j)) {
+    if (lg) {
+        memset(lg, 0, sizeof(*lg));
+        lg->iter = t;
+        lg->rank_before = -1;
+    }
+    if (choice < 0) {
+        found = try_flip(w, prm, t, &i, &j, &X, &role);
+    } else {
+        int K = prm->flip_tries, any = 0;
+        w->c.attempts += K;
+        for (int a = 0; a < K; ++a)
+            if (or_attempt_candidate(s, prm->seed, t, a, &i, &j, &X, &role) > 0) any = 1;
+        if (choice == 255) {
+            if (any) return 1;
+            found = s->r >= 2 && fallback_flip(w, prm, t, &i, &j, &X, &role);
+        } else {
+            if (choice >= K) return 1;
+            if (or_attempt_candidate(s, prm->seed, t, choice, &i, &j, &X, &role) == 0) return 1;
+            found = 1;
+        }
+    }
+    if (!found) {
         /* Algorithm 1: no flip -> expand, continue */
         w->c.dead_ends++;
         expand(w, prm, t);
         restart_check(w, prm, t);
-        return;
+        if (lg) lg->rank_after = s->r;
+        return 0;
     }
+    if (lg) {
+        log_factors(s, i, j, X, role, lg);
+        lg->rank_before = s->r;
+    }
+    or_flip(s, i, j, X, shared_sign(s, i, j, X), role);
     w->c.flips++;
 
     /* a flip that makes a factor zero is a reduction edge: the zero term
@@ -711,6 +772,56 @@ static void one_iteration(or_walk *w, const or_params *prm, int64_t t)
     if ((uint64_t)g[2] < prm->t_expand && s->r <= w->best_rank + 2 && s->r < prm->r_cap)
         expand(w, prm, t);
     restart_check(w, prm, t);
+    if (lg) lg->rank_after = s->r;
+    return 0;
+}
+
+int or_attempt_candidate(const or_scheme *s, uint64_t seed, int64_t t, int a, int *pi, int *pj,
+                         int *pX, int *prole)
+{
+    uint32_t rw[4];
+    int j = -1, sg = 0, role = 0;
+    if (s->r < 2) return 0;
+    draw(seed, t, (uint32_t)a, 0, rw);
+    int i = uniform_below(rw[0], s->r);
+    int X = uniform_below(rw[1], 3);
+    int n = attempt_candidates(s, i, X, -1, &j, &sg, &role);
+    if (n == 0) return 0;
+    attempt_candidates(s, i, X, uniform_below(rw[2], n), &j, &sg, &role);
+    *pi = i; *pj = j; *pX = X; *prole = role;
+    return n;
+}
+
+void or_walk_run_logged(or_walk *w, const or_params *prm, int64_t n_iters, or_log *log,
+                        int64_t log_cap, int32_t format_slot)
+{
+    for (int64_t step = 0; step < n_iters; ++step) {
+        if (w->best_rank <= prm->target_rank) w->done = 1;
+        if (w->done || w->t >= prm->max_iters) return;
+        int64_t t = w->t + 1;
+        or_log *lg = (log && t <= log_cap) ? &log[t - 1] : NULL;
+        one_iteration(w, prm, t, -1, lg);
+        if (lg) lg->format_slot = format_slot;
+        w->t = t;
+    }
+    if (w->best_rank <= prm->target_rank) w->done = 1;
+}
+
+void or_walk_run_choices(or_walk *w, const or_params *prm, int64_t n_iters,
+                         const uint8_t *choices, int64_t n_choices, int64_t *bad)
+{
+    for (int64_t step = 0; step < n_iters; ++step) {
+        if (w->best_rank <= prm->target_rank) w->done = 1;
+        if (w->done || w->t >= prm->max_iters) return;
+        int64_t t = w->t + 1;
+        if (t > n_choices) return;
+        if (one_iteration(w, prm, t, choices[t - 1], NULL)) {
+            ++*bad;
+            return;
+        }
+        w->t = t;
+    }
+    if (w->best_rank <= prm->target_rank) w->done = 1;
 }
 
 void or_walk_run(or_walk *w, const or_params *prm, int64_t n_iters)
@@ -719,7 +830,7 @@ void or_walk_run(or_walk *w, const or_params *prm, int64_t n_iters)
         if (w->best_rank <= prm->target_rank) w->done = 1;
         if (w->done || w->t >= prm->max_iters) return;
         int64_t t = w->t + 1;
-        one_iteration(w, prm, t);
+        one_iteration(w, prm, t, -1, NULL);
         w->t = t;
     }
     if (w->best_rank <= prm->target_rank) w->done = 1;

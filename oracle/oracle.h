@@ -89,6 +89,34 @@ typedef struct {
 void or_walk_init(or_walk *w, const or_scheme *start);
 void or_walk_run(or_walk *w, const or_params *prm, int64_t n_iters);
 
+/* One logged iteration: the applied flip's two terms before the flip, in role
+ * order (x_i, y_i, z_i, x_j, y_j, z_j), as (non-zero mask, minus mask) pairs;
+ * rank before and after the iteration; rank_before = -1 without a flip. */
+typedef struct {
+    int64_t iter;
+    int32_t rank_before, rank_after, format_slot, reserved;
+    uint64_t f[12];
+    uint64_t pad;
+} or_log;
+
+/* or_walk_run that also logs iteration t to log[t-1] while t <= log_cap */
+void or_walk_run_logged(or_walk *w, const or_params *prm, int64_t n_iters, or_log *log,
+                        int64_t log_cap, int32_t format_slot);
+
+/* Walk with externally chosen proposals: at iteration t the first
+ * prm->flip_tries attempts each yield their candidate (as in try_flip);
+ * choices[t-1] names the attempt applied (255 = none had a candidate, then
+ * the fallback search runs).  Counts choices that name an attempt without a
+ * candidate, or 255 while one had a candidate, in *bad (the walk then stops).
+ * choices covers iterations 1..n_choices. */
+void or_walk_run_choices(or_walk *w, const or_params *prm, int64_t n_iters,
+                         const uint8_t *choices, int64_t n_choices, int64_t *bad);
+
+/* The candidate of flip attempt a at iteration t of a walk in state s: returns
+ * the number of candidates of the attempt (0: none) and the chosen one. */
+int or_attempt_candidate(const or_scheme *s, uint64_t seed, int64_t t, int a, int *pi, int *pj,
+                         int *pX, int *prole);
+
 /* run walks first_walk .. first_walk+n_walks-1 (seed = base_seed + walk id)
  * from one start scheme on n_threads host threads, n_iters iterations each */
 void or_run_many(const or_scheme *start, const or_params *prm, uint64_t base_seed,

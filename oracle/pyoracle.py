@@ -234,3 +234,49 @@ def split(s: Scheme, i, j, perm) -> bool:
 
 def remove_zero_terms(s: Scheme) -> int:
     return int(lib().or_remove_zero_terms(C.byref(s)))
+
+
+class Log(C.Structure):
+    _fields_ = [("iter", C.c_int64), ("rank_before", C.c_int32), ("rank_after", C.c_int32),
+                ("format_slot", C.c_int32), ("reserved", C.c_int32), ("f", C.c_uint64 * 12),
+                ("pad", C.c_uint64)]
+
+
+def _bind_learned():
+    L = lib()
+    if not getattr(L, "_learned_bound", False):
+        P = C.POINTER
+        L.or_walk_run_logged.argtypes = [P(Walk), P(Params), C.c_int64, P(Log), C.c_int64,
+                                         C.c_int32]
+        L.or_walk_run_choices.argtypes = [P(Walk), P(Params), C.c_int64, P(C.c_uint8), C.c_int64,
+                                          P(C.c_int64)]
+        L.or_attempt_candidate.argtypes = [P(Scheme), C.c_uint64, C.c_int64, C.c_int,
+                                           P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_int)]
+        L._learned_bound = True
+    return L
+
+
+def run_logged(w: Walk, prm: Params, n_iters: int, log_cap: int, format_slot: int):
+    logs = (Log * max(log_cap, 1))()
+    _bind_learned().or_walk_run_logged(C.byref(w), C.byref(prm), n_iters, logs, log_cap,
+                                       format_slot)
+    return logs
+
+
+def run_choices(w: Walk, prm: Params, n_iters: int, choices):
+    arr = np.ascontiguousarray(choices, dtype=np.uint8)
+    bad = C.c_int64(0)
+    _bind_learned().or_walk_run_choices(C.byref(w), C.byref(prm), n_iters,
+                                        arr.ctypes.data_as(C.POINTER(C.c_uint8)), arr.size,
+                                        C.byref(bad))
+    return int(bad.value)
+
+
+def attempt_candidate(s: Scheme, seed: int, t: int, a: int):
+    """-> None or (n, i, j, X, role)"""
+    i, j, X, role = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    n = _bind_learned().or_attempt_candidate(C.byref(s), seed, t, a, C.byref(i), C.byref(j),
+                                             C.byref(X), C.byref(role))
+    if n == 0:
+        return None
+    return n, i.value, j.value, X.value, role.value

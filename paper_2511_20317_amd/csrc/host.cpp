@@ -412,3 +412,5 @@ tsf_status tsf_unpack(const uint64_t *packed, const tsf_dims *d, tsf_scheme *out
 }
 
 }  // extern "C"
+
+extern "C" int32_t tsf_format_slot(int32_t m, int32_t n, int32_t p) { return format_slot(m, n, p); }

@@ -105,3 +105,32 @@ enum {
     C_ITERS = 0, C_FLIPS, C_ATTEMPTS, C_FALLBACKS, C_DEAD_ENDS, C_ZERO_REMOVED, C_MERGES,
     C_EXPANDS, C_EXPAND_FAILS, C_RESTARTS, C_EQ_ACCEPTS, C_IMPROVEMENTS, C_NUM
 };
+
+// Slot of a format in the proposal network's one-hot: fifteen small formats
+// with their dimensions sorted, 15 for any other.
+TSF_HD int format_slot(int m, int n, int p)
+{
+    int a = m, b = n, c = p, x;
+    if (a > b) { x = a; a = b; b = x; }
+    if (b > c) { x = b; b = c; c = x; }
+    if (a > b) { x = a; a = b; b = x; }
+    const int key = a * 100 + b * 10 + c;
+    switch (key) {
+    case 222: return 0;
+    case 223: return 1;
+    case 224: return 2;
+    case 233: return 3;
+    case 234: return 4;
+    case 333: return 5;
+    case 334: return 6;
+    case 244: return 7;
+    case 344: return 8;
+    case 335: return 9;
+    case 444: return 10;
+    case 345: return 11;
+    case 445: return 12;
+    case 455: return 13;
+    case 555: return 14;
+    default: return 15;
+    }
+}

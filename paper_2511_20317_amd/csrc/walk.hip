@@ -119,6 +119,19 @@ __global__ void __launch_bounds__(256) verify_kernel(const tsf_walk_header *hdr,
     if (threadIdx.x == 0) n_violated[q] = bad_sh;
 }
 
+// feature rows of the proposal network from log records, one row per thread
+__global__ void __launch_bounds__(256) features_kernel(const tsf_flip_log *log, int64_t n,
+                                                       uint16_t *X)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const tsf_flip_log &lg = log[q];
+    uint64_t f[12];
+    for (int e = 0; e < 12; ++e) f[e] = lg.f[e];
+    const int slot = lg.format_slot < 0 || lg.format_slot > 15 ? 15 : lg.format_slot;
+    write_feature_row(X + q * 512, f, slot, lg.rank_before);
+}
+
 // ---------------------------------------------------------------------------
 // host side: kernel table and launch
 // ---------------------------------------------------------------------------
@@ -195,10 +208,22 @@ tsf_status tsf_walk_init(tsf_ctx *ctx, const tsf_walk_batch *b, void *hip_stream
     return TSF_OK;
 }
 
-tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
-                    int64_t n_iters, const tsf_launch *launch, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+struct Launch {
+    KernelFn fn;
+    dim3 grid, block;
+    size_t lds;
+    int g;
+    bool ap;
+};
+
+// validate a walk call and build its kernel arguments and launch shape
+tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int64_t n_iters,
+                        const tsf_launch *launch, KArgs &a, Launch &L)
 {
-    (void)ctx;
     tsf_status st = check_batch(b);
     if (st) return st;
     if (!prm) return tsf_fail(TSF_E_ARG, "null params");
@@ -207,7 +232,7 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
     if (prm->t_eq > (1ull << 32) || prm->t_reduce > (1ull << 32) || prm->t_expand > (1ull << 32))
         return tsf_fail(TSF_E_ARG, "a probability threshold exceeds 2^32");
     if (n_iters < 0) return tsf_fail(TSF_E_ARG, "n_iters < 0");
-    if (b->n_walks == 0 || n_iters == 0) return TSF_OK;
+    if (b->log && b->log_cap < 0) return tsf_fail(TSF_E_ARG, "log_cap < 0");
     int strategy = launch ? launch->strategy : 0;
     if (strategy < 0 || strategy > 2) return tsf_fail(TSF_E_ARG, "strategy %d not in 0..2", strategy);
     if (strategy == 0) strategy = b->capacity <= 64 ? 1 : 2;
@@ -226,15 +251,14 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
         return tsf_fail(TSF_E_CAPACITY, "capacity %d needs more than 8 slots at %d lanes/walk",
                         b->capacity, g);
     const bool wide = b->max_len > 32;
-    KernelFn fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, ap);
-    if (!fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
+    L.fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, ap);
+    if (!L.fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
     const size_t word = wide ? 8 : 4;
     const int walks_per_wave = 64 / g;
     const int cap2 = b->capacity + (b->capacity & 1);
-    const size_t lds = (size_t)wpb * walks_per_wave * cap2 * 6 * word;
-    if (lds > 160 * 1024)
-        return tsf_fail(TSF_E_CAPACITY, "%zu bytes of LDS per workgroup exceed 160 KiB", lds);
-    KArgs a;
+    L.lds = (size_t)wpb * walks_per_wave * cap2 * 6 * word;
+    if (L.lds > 160 * 1024)
+        return tsf_fail(TSF_E_CAPACITY, "%zu bytes of LDS per workgroup exceed 160 KiB", L.lds);
     std::memset(&a, 0, sizeof a);
     a.base_seed = prm->base_seed;
     a.first_walk_id = prm->first_walk_id;
@@ -252,6 +276,8 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
     a.mode = b->mode;
     a.max_len = b->max_len;
     a.cap2 = cap2;
+    a.log = b->log;
+    a.log_cap = b->log ? b->log_cap : 0;
     a.hdr = b->hdr;
     a.cur = b->cur;
     a.best = b->best;
@@ -259,14 +285,89 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
     a.rec = b->rec;
     const int64_t walks_per_block = (int64_t)wpb * walks_per_wave;
     const int64_t blocks = (b->n_walks + walks_per_block - 1) / walks_per_block;
-    hipStream_t hs = (hipStream_t)hip_stream;
-    if (lds > 64 * 1024 &&
-        hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
-        return tsf_fail(TSF_E_DEVICE, "cannot raise the LDS limit to %zu bytes", lds);
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, hs, a);
+    L.grid = dim3((unsigned)blocks);
+    L.block = dim3(64 * wpb);
+    L.g = g;
+    L.ap = ap;
+    if (L.lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void *)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)L.lds) != hipSuccess)
+        return tsf_fail(TSF_E_DEVICE, "cannot raise the LDS limit to %zu bytes", L.lds);
+    return TSF_OK;
+}
+
+tsf_status run(const Launch &L, const KArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(L.fn, L.grid, L.block, L.lds, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return tsf_fail(TSF_E_DEVICE, "walk launch failed: %s", hipGetErrorString(e));
+    return TSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                    int64_t n_iters, const tsf_launch *launch, void *hip_stream)
+{
+    (void)ctx;
+    KArgs a;
+    Launch L;
+    tsf_status st = prepare_walk(prm, b, n_iters, launch, a, L);
+    if (st) return st;
+    if (b->n_walks == 0 || n_iters == 0) return TSF_OK;
+    return run(L, a, (hipStream_t)hip_stream);
+}
+
+tsf_status tsf_walk_learned(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                            const tsf_mlp *net, const tsf_learn_ws *ws, int64_t n_iters,
+                            const tsf_launch *launch, void *hip_stream)
+{
+    (void)ctx;
+    KArgs a;
+    Launch L;
+    tsf_status st = prepare_walk(prm, b, n_iters, launch, a, L);
+    if (st) return st;
+    if (!L.ap)
+        return tsf_fail(TSF_E_CAPACITY,
+                        "learned proposals use the attempt-parallel strategy (capacity <= 64)");
+    const int K = prm->flip_tries;
+    if (K > L.g - 1 || K > kLearnRows)
+        return tsf_fail(TSF_E_ARG, "flip_tries %d exceeds the %d attempts scored at %d lanes/walk",
+                        K, L.g - 1 < kLearnRows ? L.g - 1 : kLearnRows, L.g);
+    if (!net || !ws || !ws->cand || !ws->feat || !ws->h1 || !ws->h2 || !ws->logit)
+        return tsf_fail(TSF_E_ARG, "null learned-proposal buffer");
+    if (ws->choice && ws->choice_cap < 0) return tsf_fail(TSF_E_ARG, "choice_cap < 0");
+    if (b->n_walks == 0 || n_iters == 0) return TSF_OK;
+    const int64_t rows = (int64_t)b->n_walks * kLearnRows;
+    if (rows > 0x7FFFFFFF) return tsf_fail(TSF_E_CAPACITY, "too many candidate rows");
+    a.learn_k = K;
+    a.cand = ws->cand;
+    a.feat = ws->feat;
+    a.logit = ws->logit;
+    a.choice = ws->choice;
+    a.choice_cap = ws->choice ? ws->choice_cap : 0;
+    a.n_iters = 1;
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (int64_t it = 0; it < n_iters; ++it) {
+        a.phase = 1;
+        if ((st = run(L, a, s))) return st;
+        if ((st = tsf_mlp_fwd(net, ws->feat, (int32_t)rows, ws->h1, ws->h2, ws->logit, hip_stream)))
+            return st;
+        a.phase = 2;
+        if ((st = run(L, a, s))) return st;
+    }
+    return TSF_OK;
+}
+
+tsf_status tsf_features_from_log(const tsf_flip_log *log, int64_t n, uint16_t *X, void *hip_stream)
+{
+    if (n < 0 || (n > 0 && (!log || !X))) return tsf_fail(TSF_E_ARG, "bad feature arguments");
+    if (n == 0) return TSF_OK;
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)hip_stream, log, n, X);
+    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "feature launch failed");
     return TSF_OK;
 }
 

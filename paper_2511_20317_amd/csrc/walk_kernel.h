@@ -58,7 +58,49 @@ struct KArgs {
     uint64_t *best;
     const uint64_t *start;
     tsf_record *rec;
+    // training log (uniform proposals); null = off
+    tsf_flip_log *log;
+    int32_t log_cap;
+    // learned proposal: attempts scored per iteration, and the buffers
+    int32_t learn_k;
+    uint32_t *cand;      // 8 per walk
+    uint16_t *feat;      // 8 rows of 512 bf16 per walk
+    const float *logit;  // 8 per walk
+    uint8_t *choice;     // choice_cap per walk, optional
+    int32_t choice_cap;
+    int32_t phase;       // 0: n_iters uniform iterations; 1: propose; 2: apply
 };
+
+constexpr int kLearnRows = 8;  // candidate rows per walk in the learned workspace
+
+// bf16 bit patterns of +1 and -1
+constexpr uint16_t kBf16One = 0x3F80, kBf16MinusOne = 0xBF80;
+
+// Feature row of the proposal network (512 bf16): six blocks of 64 entries
+// (+1 / -1 / 0 of the factors x_i y_i z_i x_j y_j z_j), the format one-hot at
+// 384 + slot, the rank one-hot at 400 + min(rank, 95), zeros elsewhere.
+__device__ __forceinline__ void write_feature_row(uint16_t *row, const uint64_t (&f)[12], int slot,
+                                                  int rank)
+{
+    uint32_t *w32 = reinterpret_cast<uint32_t *>(row);
+    for (int b = 0; b < 6; ++b) {
+        const uint64_t d = f[2 * b], s = f[2 * b + 1];
+#pragma unroll 4
+        for (int e = 0; e < 64; e += 2) {
+            const uint32_t lo = ((d >> e) & 1) ? (((s >> e) & 1) ? kBf16MinusOne : kBf16One) : 0u;
+            const uint32_t hi =
+                ((d >> (e + 1)) & 1) ? (((s >> (e + 1)) & 1) ? kBf16MinusOne : kBf16One) : 0u;
+            w32[(b * 64 + e) >> 1] = lo | (hi << 16);
+        }
+    }
+    const int fs = 384 + slot;
+    const int rs = 400 + (rank < 95 ? (rank < 0 ? 0 : rank) : 95);
+    for (int e = 384; e < 512; e += 2) {
+        const uint32_t lo = (e == fs || e == rs) ? kBf16One : 0u;
+        const uint32_t hi = (e + 1 == fs || e + 1 == rs) ? kBf16One : 0u;
+        w32[e >> 1] = lo | (hi << 16);
+    }
+}
 
 // role permutations (X,Y,Z) of (U,V,W), lexicographic
 static __constant__ int8_t kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
@@ -112,6 +154,9 @@ struct Walker {
     Philox4 pb;
     // zero-factor flags of the two terms of the last flip
     bool zfi, zfj;
+    // this iteration is written to the training log
+    bool logging;
+    int fmt_slot;
     // largest rank of the walks of this wavefront, rounded up to even: the
     // wave-uniform bound of the attempt-parallel match scan
     int scan_end;
@@ -268,6 +313,16 @@ struct Walker {
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
         const int Y = role ? B : A, Z = role ? A : B;
         const int sg = rel(ld(i, X), ld(j, X), X);
+        if (logging && gl == 0) {
+            tsf_flip_log *lg = a->log + (size_t)walk * a->log_cap + (t - 1);
+            const TV<T> fv[6] = {ld(i, X), ld(i, Y), ld(i, Z), ld(j, X), ld(j, Y), ld(j, Z)};
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                lg->f[2 * q] = (uint64_t)fv[q].d;
+                lg->f[2 * q + 1] = (uint64_t)fv[q].s;
+            }
+            lg->rank_before = r;
+        }
         TV<T> ny, nz;
         axpy(sg, ld(i, Y), ld(j, Y), ny);
         axpy(-1, ld(j, Z), ld(i, Z), nz);
@@ -749,20 +804,24 @@ struct Walker {
         }
     }
 
-    __device__ void iteration()
+    __device__ void begin_iteration()
     {
         cnt[C_ITERS]++;
-        {
-            // this iteration's draws: lane q < G-1 -> flip attempt q, lane G-1 -> gates
-            const bool gate_lane = gl == G - 1;
-            pb = walk_block(seed, t, gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
-        }
-        int fi = -1, fj = -1;
-        if (!try_flip(fi, fj)) {
+        // this iteration's draws: lane q < G-1 -> flip attempt q, lane G-1 -> gates
+        const bool gate_lane = gl == G - 1;
+        pb = walk_block(seed, t, gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
+        logging = a->log != nullptr && t <= a->log_cap;
+    }
+
+    // everything of Algorithm 1 after try_flip
+    __device__ void finish_iteration(bool found, int fi, int fj)
+    {
+        if (!found) {
             // Algorithm 1: no flip -> expand, continue
             cnt[C_DEAD_ENDS]++;
             expand();
             restart_check();
+            write_log(false);
             return;
         }
         cnt[C_FLIPS]++;
@@ -802,6 +861,112 @@ struct Walker {
         if ((uint64_t)g1 < a->t_reduce) cnt[C_MERGES] += (uint32_t)reduce(tr0, tr1);
         if ((uint64_t)g2 < a->t_expand && r <= best_rank + 2 && r < r_cap) expand();
         restart_check();
+        write_log(true);
+    }
+
+    __device__ void write_log(bool flipped)
+    {
+        if (logging && gl == 0) {
+            tsf_flip_log *lg = a->log + (size_t)walk * a->log_cap + (t - 1);
+            lg->iter = t;
+            if (!flipped) {
+                lg->rank_before = -1;
+                for (int q = 0; q < 12; ++q) lg->f[q] = 0;
+            }
+            lg->rank_after = r;
+            lg->format_slot = fmt_slot;
+            lg->reserved = 0;
+            lg->pad = 0;
+        }
+    }
+
+    __device__ void iteration()
+    {
+        begin_iteration();
+        int fi = -1, fj = -1;
+        const bool found = try_flip(fi, fj);
+        finish_iteration(found, fi, fj);
+    }
+
+    // ---------------------------------------------------------- learned
+    // Phase 1 of a learned iteration: attempt q < K (one per lane) yields
+    // its candidate exactly as with uniform proposals; lane q writes the
+    // candidate (i | j<<8 | X<<16 | role<<18, or ~0 without one) and its
+    // feature row.  The walk state is not changed.
+    __device__ void propose()
+    {
+        const bool gate_lane = gl == G - 1;
+        pb = walk_block(seed, t, gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
+        const int K = a->learn_k;
+        uint32_t desc = ~0u;
+        if (r >= 2) {
+            update_scan_end();
+            const int i = (int)below(pb.x[0], (uint32_t)r);
+            const int X = (int)below(pb.x[1], 3u);
+            uint64_t m0 = 0, m1 = 0;
+            if (gl < K) candidates_ap(i, X, m0, m1);
+            const int n0 = popc64(m0), n = n0 + popc64(m1);
+            if (n > 0) {
+                int c = (int)below(pb.x[2], (uint32_t)n);
+                const int role = c >= n0;
+                if (role) c -= n0;
+                const int j = kth_bit(role ? m1 : m0, c);
+                desc = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)X << 16) |
+                       ((uint32_t)role << 18);
+                const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
+                const int Y = role ? B : A, Z = role ? A : B;
+                const TV<T> fv[6] = {ld(i, X), ld(i, Y), ld(i, Z), ld(j, X), ld(j, Y), ld(j, Z)};
+                uint64_t f[12];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    f[2 * q] = (uint64_t)fv[q].d;
+                    f[2 * q + 1] = (uint64_t)fv[q].s;
+                }
+                write_feature_row(a->feat + ((size_t)walk * kLearnRows + gl) * 512, f, fmt_slot, r);
+            }
+        }
+        if (gl < kLearnRows) a->cand[(size_t)walk * kLearnRows + gl] = desc;
+    }
+
+    // Phase 2: apply the best-scored candidate (ties: the lower attempt), or
+    // run the uniform fallback search when no attempt had a candidate.
+    __device__ void apply_learned()
+    {
+        begin_iteration();
+        const int K = a->learn_k;
+        uint32_t desc = ~0u;
+        float score = -__builtin_inff();
+        if (gl < K) {
+            desc = a->cand[(size_t)walk * kLearnRows + gl];
+            const float l = a->logit[(size_t)walk * kLearnRows + gl];
+            if (desc != ~0u) score = (l == l) ? l : -__builtin_inff();
+        }
+        const bool valid = desc != ~0u;
+        float best = score;
+        for (int off = 1; off < G; off <<= 1) best = fmaxf(best, __shfl_xor(best, off, G));
+        const uint64_t win_mask = gballot(valid && score == best);
+        cnt[C_ATTEMPTS] += (uint32_t)K;
+        int fi = -1, fj = -1;
+        bool found;
+        uint8_t choice = 255;
+        if (win_mask) {
+            const int win = __builtin_ctzll(win_mask);
+            const uint32_t d = from_lane(desc, win);
+            fi = d & 0xFF;
+            fj = (d >> 8) & 0xFF;
+            apply_flip(fi, fj, (d >> 16) & 3, (d >> 18) & 1, zfi, zfj);
+            found = true;
+            choice = (uint8_t)win;
+        } else {
+            found = false;
+            if (r >= 2) {
+                update_scan_end();
+                found = fallback_ap(fi, fj);
+            }
+        }
+        if (a->choice && gl == 0 && t <= a->choice_cap)
+            a->choice[(size_t)walk * a->choice_cap + (t - 1)] = choice;
+        finish_iteration(found, fi, fj);
     }
 };
 
@@ -854,13 +1019,32 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
     wk.plateau_start = h->plateau_start;
 #pragma unroll
     for (int c = 0; c < C_NUM; ++c) wk.cnt[c] = 0;
+    wk.logging = false;
+    wk.fmt_slot = format_slot(m, n, p);
     wk.load_scheme(a.cur + (size_t)walk * a.cap * 6, wk.r);
 
-    for (int64_t it = 0; it < a.n_iters; ++it) {
+    if constexpr (AP) {
+        if (a.phase == 1) {
+            // learned proposal, phase 1: candidates and feature rows only
+            if (wk.best_rank <= wk.target || wk.t >= a.max_iters) return;
+            wk.t += 1;
+            wk.propose();
+            return;
+        }
+    }
+    if (AP && a.phase == 2) {
         if (wk.best_rank <= wk.target) done = 1;
-        if (done || wk.t >= a.max_iters) break;
-        wk.t += 1;
-        wk.iteration();
+        if (!done && wk.t < a.max_iters) {
+            wk.t += 1;
+            if constexpr (AP) wk.apply_learned();
+        }
+    } else {
+        for (int64_t it = 0; it < a.n_iters; ++it) {
+            if (wk.best_rank <= wk.target) done = 1;
+            if (done || wk.t >= a.max_iters) break;
+            wk.t += 1;
+            wk.iteration();
+        }
     }
     if (wk.best_rank <= wk.target) done = 1;
 

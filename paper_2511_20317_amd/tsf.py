@@ -53,7 +53,14 @@ class WalkBatchC(C.Structure):
     _fields_ = [("n_walks", C.c_int32), ("capacity", C.c_int32), ("rec_cap", C.c_int32),
                 ("mode", C.c_int32), ("max_len", C.c_int32), ("reserved", C.c_int32),
                 ("hdr", C.c_void_p), ("cur", C.c_void_p), ("best", C.c_void_p),
-                ("start", C.c_void_p), ("rec", C.c_void_p)]
+                ("start", C.c_void_p), ("rec", C.c_void_p), ("log", C.c_void_p),
+                ("log_cap", C.c_int32), ("reserved2", C.c_int32)]
+
+
+class LearnWsC(C.Structure):
+    _fields_ = [("cand", C.c_void_p), ("feat", C.c_void_p), ("h1", C.c_void_p),
+                ("h2", C.c_void_p), ("logit", C.c_void_p), ("choice", C.c_void_p),
+                ("choice_cap", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Launch(C.Structure):
@@ -113,6 +120,10 @@ def lib():
                              C.c_void_p]),
             ("tsf_mlp_step", [P(MlpC), C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
                               C.c_void_p]),
+            ("tsf_features_from_log", [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+            ("tsf_walk_learned", [C.c_void_p, P(WalkParams), P(WalkBatchC), P(MlpC), P(LearnWsC),
+                                  C.c_int64, P(Launch), C.c_void_p]),
+            ("tsf_format_slot", [C.c_int32, C.c_int32, C.c_int32]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -273,9 +284,10 @@ class WalkBatch:
     out group after group.  All groups share one mode.
     """
 
-    def __init__(self, groups, capacity=None, rec_cap=64, device="cuda"):
+    def __init__(self, groups, capacity=None, rec_cap=64, device="cuda", log_cap=0):
         import torch
         self.torch = torch
+        self.log_cap = int(log_cap)
         modes = {g[0].mode for g in groups}
         if len(modes) != 1:
             raise ValueError("one mode per batch")
@@ -308,11 +320,15 @@ class WalkBatch:
         self.best = torch.zeros_like(self.start)
         self.rec = torch.zeros((self.n_walks, max(self.rec_cap, 1), 2), dtype=torch.int64,
                                device=dev)
+        self.log = (torch.zeros((self.n_walks, self.log_cap, 16), dtype=torch.int64, device=dev)
+                    if self.log_cap else None)
 
     def c(self):
         return WalkBatchC(self.n_walks, self.capacity, self.rec_cap, self.mode, self.max_len, 0,
                           self.hdr.data_ptr(), self.cur.data_ptr(), self.best.data_ptr(),
-                          self.start.data_ptr(), self.rec.data_ptr())
+                          self.start.data_ptr(), self.rec.data_ptr(),
+                          self.log.data_ptr() if self.log is not None else None,
+                          self.log_cap, 0)
 
     def _stream(self):
         return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
@@ -325,6 +341,12 @@ class WalkBatch:
         la = Launch(lanes_per_walk, waves_per_block, strategy)
         check(lib().tsf_walk(ctx.ptr, C.byref(prm), C.byref(self.c()), int(n_iters),
                              C.byref(la), self._stream()))
+
+    def walk_learned(self, ctx: Context, prm: WalkParams, net, ws, n_iters: int,
+                     lanes_per_walk=0, waves_per_block=0):
+        la = Launch(lanes_per_walk, waves_per_block, 1)
+        check(lib().tsf_walk_learned(ctx.ptr, C.byref(prm), C.byref(self.c()), C.byref(net.c()),
+                                     C.byref(ws.c()), int(n_iters), C.byref(la), self._stream()))
 
     def verify_device(self, which=1):
         """Brent check of cur (0), best (1) or start (2) of every walk on the GPU."""
@@ -447,3 +469,47 @@ def bf16_bits(a):
 def bf16_to_float(bits):
     b = np.asarray(bits).view(np.uint16).astype(np.uint32) << 16
     return b.view(np.float32).astype(np.float64)
+
+
+class LearnWorkspace:
+    """Device workspace of tsf_walk_learned for a batch of n_walks walks."""
+
+    def __init__(self, n_walks, choice_cap=0, device="cuda"):
+        import torch
+        rows = 8 * n_walks
+        dev = torch.device(device)
+        self.cand = torch.zeros(rows, dtype=torch.int32, device=dev)
+        self.feat = torch.zeros((rows, MLP_IN), dtype=torch.int16, device=dev)
+        self.h1 = torch.zeros((rows, MLP_HID), dtype=torch.int16, device=dev)
+        self.h2 = torch.zeros_like(self.h1)
+        self.logit = torch.zeros(rows, dtype=torch.float32, device=dev)
+        self.choice_cap = int(choice_cap)
+        self.choice = (torch.zeros((n_walks, self.choice_cap), dtype=torch.uint8, device=dev)
+                       if self.choice_cap else None)
+
+    def c(self):
+        return LearnWsC(self.cand.data_ptr(), self.feat.data_ptr(), self.h1.data_ptr(),
+                        self.h2.data_ptr(), self.logit.data_ptr(),
+                        self.choice.data_ptr() if self.choice is not None else None,
+                        self.choice_cap, 0)
+
+
+LOG_DTYPE = np.dtype([("iter", "<i8"), ("rank_before", "<i4"), ("rank_after", "<i4"),
+                      ("format_slot", "<i4"), ("reserved", "<i4"), ("f", "<u8", (12,)),
+                      ("pad", "<u8")])
+assert LOG_DTYPE.itemsize == 128
+
+
+def features_from_log(log_tensor, n=None):
+    """Device log records (int64 tensor, 16 words per record) -> bf16 rows (int16 tensor)."""
+    import torch
+    flat = log_tensor.reshape(-1, 16)
+    n = flat.shape[0] if n is None else n
+    X = torch.empty((n, MLP_IN), dtype=torch.int16, device=flat.device)
+    check(lib().tsf_features_from_log(C.c_void_p(flat.data_ptr()), n, C.c_void_p(X.data_ptr()),
+                                      C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return X
+
+
+def format_slot(m, n, p):
+    return int(lib().tsf_format_slot(m, n, p))

@@ -1,0 +1,156 @@
+"""The learned proposal on the GPU against the oracle: training logs and
+feature rows bit for bit, learned walks replayed by the oracle from the
+logged choices bit for bit, and the network's scores of the proposed
+candidates against the fp64 network oracle."""
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from oracle import pyoracle as O
+from paper_2511_20317_amd import tsf
+from tests.gpu_parity import compare, oracle_params, oracle_start
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    return tsf.Context()
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def test_format_slot_tables_agree():
+    for m in range(1, 9):
+        for n in range(1, 9):
+            for p in range(1, 9):
+                assert tsf.format_slot(m, n, p) == ref.format_slot(m, n, p)
+
+
+@pytest.mark.parametrize("fmt,r_cap", [((2, 2, 2), 16), ((3, 3, 3), 35), ((3, 4, 4), 56)])
+def test_training_log_matches_oracle(ctx, fmt, r_cap):
+    s = tsf.init_scheme(*fmt)
+    groups = [(s, 16, r_cap, 0)]
+    log_cap = 400
+    prm = tsf.walk_params(base_seed=31, max_iters=500, plateau=150, t_expand=1 << 28)
+    b = tsf.WalkBatch(groups, rec_cap=16, log_cap=log_cap)
+    b.init(ctx)
+    b.walk(ctx, prm, 500)
+    _sync()
+    glog = b.log.cpu().numpy().reshape(16, log_cap, 16).view(np.uint8).reshape(16, log_cap, 128)
+    slot = ref.format_slot(*fmt)
+    for w in range(16):
+        ow = O.new_walk(oracle_start(s))
+        ologs = O.run_logged(ow, oracle_params(prm, w, r_cap, 0), 500, log_cap, slot)
+        want = np.ctypeslib.as_array(ologs).view(np.uint8).reshape(log_cap, 128)
+        assert np.array_equal(glog[w], want), "walk %d" % w
+
+
+def test_features_from_log_match_oracle(ctx):
+    import torch
+    s = tsf.init_scheme(3, 3, 3)
+    b = tsf.WalkBatch([(s, 8, 35, 0)], rec_cap=4, log_cap=64)
+    b.init(ctx)
+    b.walk(ctx, tsf.walk_params(base_seed=3, max_iters=64), 64)
+    X = tsf.features_from_log(b.log)
+    _sync()
+    rec = b.log.cpu().numpy().reshape(-1, 16)
+    got = tsf.bf16_to_float(X.cpu().numpy())
+    for q in range(rec.shape[0]):
+        r = rec[q].view(tsf.LOG_DTYPE)[0]
+        f = [ref.masks_to_vec(int(r["f"][2 * b_]), int(r["f"][2 * b_ + 1])) for b_ in range(6)]
+        want = ref.feature_row(f, int(r["format_slot"]), int(r["rank_before"]))
+        assert np.array_equal(got[q], want), q
+    del torch
+
+
+def _random_net(seed):
+    p = ref.init_params(seed)
+    rng = np.random.default_rng(seed)
+    p["b1"] = rng.standard_normal(ref.D_H) * 0.1
+    p["b2"] = rng.standard_normal(ref.D_H) * 0.1
+    net = tsf.Mlp()
+    net.set_params(p["W1"], p["b1"], p["W2"], p["b2"], p["w3"], p["b3"])
+    return net, p
+
+
+@pytest.mark.parametrize("fmt,r_cap,lanes", [((3, 3, 3), 35, 8), ((2, 2, 3), 20, 16),
+                                             ((3, 3, 4), 44, 8)])
+def test_learned_walk_replays_on_oracle(ctx, fmt, r_cap, lanes):
+    s = tsf.init_scheme(*fmt)
+    groups = [(s, 24, r_cap, 0)]
+    n_iters = 300
+    prm = tsf.walk_params(base_seed=17, max_iters=n_iters, plateau=120, t_expand=1 << 28)
+    net, _ = _random_net(5)
+    b = tsf.WalkBatch(groups, rec_cap=32)
+    b.init(ctx)
+    ws = tsf.LearnWorkspace(b.n_walks, choice_cap=n_iters)
+    b.walk_learned(ctx, prm, net, ws, n_iters, lanes_per_walk=lanes)
+    _sync()
+    choices = ws.choice.cpu().numpy()
+    oracle_walks = {}
+    for w in range(b.n_walks):
+        ow = O.new_walk(oracle_start(s))
+        bad = O.run_choices(ow, oracle_params(prm, w, r_cap, 0), n_iters, choices[w])
+        assert bad == 0, "walk %d: a logged choice is not a valid candidate" % w
+        oracle_walks[w] = ow
+    compare(b, oracle_walks, "learned %s" % (fmt,))
+    # the network did reorder: some applied attempt is not the first valid one
+    assert (choices[(choices != 255)] > 0).any()
+
+
+def test_learned_scores_and_choices_at_first_iteration(ctx):
+    """Iteration 1 from the start scheme: the proposed candidates and their
+    feature rows equal the oracle's, the scores equal the fp64 network within
+    the tolerance of the network tests, and the applied attempt is the best
+    scored one."""
+    s = tsf.init_scheme(3, 3, 3)
+    groups = [(s, 64, 35, 0)]
+    prm = tsf.walk_params(base_seed=99, max_iters=1)
+    net, p = _random_net(8)
+    b = tsf.WalkBatch(groups, rec_cap=4)
+    b.init(ctx)
+    ws = tsf.LearnWorkspace(b.n_walks, choice_cap=1)
+    b.walk_learned(ctx, prm, net, ws, 1)
+    _sync()
+    cand = ws.cand.cpu().numpy().view(np.uint32).reshape(-1, 8)
+    feat = tsf.bf16_to_float(ws.feat.cpu().numpy()).reshape(-1, 8, 512)
+    logit = ws.logit.cpu().numpy().reshape(-1, 8)
+    choice = ws.choice.cpu().numpy()[:, 0]
+    os_ = oracle_start(s)
+    d = O.from_c(os_)
+    slot = ref.format_slot(3, 3, 3)
+    rows, where = [], []
+    for w in range(b.n_walks):
+        seed = prm.base_seed + prm.first_walk_id + w
+        for a in range(prm.flip_tries):
+            oc = O.attempt_candidate(os_, seed, 1, a)
+            if oc is None:
+                assert cand[w, a] == 0xFFFFFFFF
+                continue
+            _, i, j, X, role = oc
+            assert cand[w, a] == i | (j << 8) | (X << 16) | (role << 18)
+            others = [k for k in range(3) if k != X]
+            Y, Z = (others[1], others[0]) if role else (others[0], others[1])
+            M = [d["U"], d["V"], d["W"]]
+            f = [M[X][i], M[Y][i], M[Z][i], M[X][j], M[Y][j], M[Z][j]]
+            row = ref.feature_row(f, slot, 27)
+            assert np.array_equal(feat[w, a], row)
+            rows.append(row)
+            where.append((w, a))
+    fr = ref.forward(p, np.array(rows))
+    tol = 2 ** -5 * (fr["m3"] + 1) + 1e-6
+    for q, (w, a) in enumerate(where):
+        assert abs(logit[w, a] - fr["logit"][q]) <= tol[q]
+    for w in range(b.n_walks):
+        valid = [a for a in range(prm.flip_tries) if cand[w, a] != 0xFFFFFFFF]
+        if not valid:
+            assert choice[w] == 255
+            continue
+        best = max(logit[w, a] for a in valid)
+        assert choice[w] == min(a for a in valid if logit[w, a] == best)
