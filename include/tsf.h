@@ -263,6 +263,24 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
 tsf_status tsf_verify_batch(const tsf_walk_batch *b, int32_t which, int64_t *n_violated,
                             void *hip_stream);
 
+/* Meta operators (Sec. 3.3.2) on every walk of a batch at once, on the GPU:
+ * the current (which = 0) or best (which = 1) scheme of walk w of `in`
+ * becomes the start scheme of walk w of `out`, after op[w]: 0 = copy,
+ * 1 = project (drop index index[w] of axis axis[w], 0 = m, 1 = n, 2 = p, then
+ * remove the terms that became zero, keeping the order of the others),
+ * 2 = extend along axis[w] (append the naive scheme of the new index, as
+ * tsf_meta_extend).  Every term is renormalised (Sec. 3.6).  out->hdr[w]
+ * receives the new format, in's mode and target rank, start_rank and
+ * r_cap = min(start_rank + r_cap_extra, out->capacity); a result that does
+ * not fit out->capacity or 64-entry factors, or an invalid op, gets
+ * start_rank = -1, which tsf_walk_init then flags.  op, axis, index: device
+ * int32 arrays of n_walks.  in and out are distinct buffers of equal n_walks.
+ * Follow with tsf_walk_init(out).  Async on the stream.
+ * Errors: TSF_E_ARG, TSF_E_DEVICE. */
+tsf_status tsf_meta_batch(const tsf_walk_batch *in, int32_t which, const int32_t *op,
+                          const int32_t *axis, const int32_t *index, int32_t r_cap_extra,
+                          const tsf_walk_batch *out, void *hip_stream);
+
 /* Expand n log records into bf16 feature rows X (device, n x 512) of the
  * proposal network: entries 0..383 the six factors (64 entries each, +-1/0),
  * 384 + format_slot one-hot, 400 + min(rank_before, 95) one-hot, the rest 0.

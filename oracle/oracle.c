@@ -449,7 +449,7 @@ int or_full_reduce(or_scheme *s)
 
 /* Project (m,n,p) -> one dimension smaller: drop index `index` of axis
  * (0 = m, 1 = n, 2 = p) from every factor it appears in, then remove the
- * terms that became zero. */
+ * terms that became zero (the others keep their order). */
 int or_project(const or_scheme *in, int axis, int index, or_scheme *out)
 {
     int m = in->m, n = in->n, p = in->p;
@@ -478,7 +478,19 @@ int or_project(const or_scheme *in, int axis, int index, or_scheme *out)
                 out->f[OR_W][l][k2 * m2 + i2] = in->f[OR_W][l][k * m + i];
             }
     }
-    or_remove_zero_terms(out);
+    /* drop the terms that became zero, keeping the order of the others */
+    int kept = 0;
+    for (int l = 0; l < out->r; ++l) {
+        if (term_has_zero_factor(out, l)) continue;
+        if (kept != l) copy_term(out, kept, l);
+        ++kept;
+    }
+    for (int l = kept; l < out->r; ++l) {
+        memset(out->f[OR_U][l], 0, OR_MAXL);
+        memset(out->f[OR_V][l], 0, OR_MAXL);
+        memset(out->f[OR_W][l], 0, OR_MAXL);
+    }
+    out->r = kept;
     for (int l = 0; l < out->r; ++l) or_normalise_term(out, l);
     return 0;
 }

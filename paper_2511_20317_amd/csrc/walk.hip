@@ -119,6 +119,118 @@ __global__ void __launch_bounds__(256) verify_kernel(const tsf_walk_header *hdr,
     if (threadIdx.x == 0) n_violated[q] = bad_sh;
 }
 
+// (r, c) of a row-major rows x cols factor -> the new position, or -1 when
+// its row or column is dropped (drop_r / drop_c, -1 for none); cols2 is the
+// new row length
+__device__ __forceinline__ uint64_t remap_mask(uint64_t mask, int cols, int cols2, int drop_r,
+                                               int drop_c)
+{
+    uint64_t o = 0;
+    for (; mask; mask &= mask - 1) {
+        const int e = __builtin_ctzll(mask);
+        const int rr = e / cols, cc = e % cols;
+        if (rr == drop_r || cc == drop_c) continue;
+        const int r2 = rr - (drop_r >= 0 && rr > drop_r), c2 = cc - (drop_c >= 0 && cc > drop_c);
+        o |= 1ull << (r2 * cols2 + c2);
+    }
+    return o;
+}
+
+// One wavefront per walk: project / extend / copy a scheme into a new start.
+__global__ void __launch_bounds__(64) meta_kernel(tsf_walk_batch in, int32_t which,
+                                                  const int32_t *op, const int32_t *axis,
+                                                  const int32_t *index, int32_t r_cap_extra,
+                                                  tsf_walk_batch out)
+{
+    const int64_t walk = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (walk >= in.n_walks) return;
+    const tsf_walk_header *h = in.hdr + walk;
+    tsf_walk_header *ho = out.hdr + walk;
+    const int m = h->m, n = h->n, p = h->p, mode = h->mode;
+    const int rank = which ? h->best_rank : h->rank;
+    const int o = op[walk], ax = axis[walk], ix = index[walk];
+    const int dims[3] = {m, n, p};
+    bool ok = m >= 1 && n >= 1 && p >= 1 && rank >= 0 && rank <= in.capacity && o >= 0 &&
+              o <= 2 && (o == 0 || (ax >= 0 && ax <= 2));
+    if (ok && o == 1) ok = dims[ax] >= 2 && ix >= 0 && ix < dims[ax];
+    const int m2 = m + (ok && ax == 0 ? (o == 1 ? -1 : o == 2 ? 1 : 0) : 0);
+    const int n2 = n + (ok && ax == 1 ? (o == 1 ? -1 : o == 2 ? 1 : 0) : 0);
+    const int p2 = p + (ok && ax == 2 ? (o == 1 ? -1 : o == 2 ? 1 : 0) : 0);
+    ok = ok && m2 * n2 <= 64 && n2 * p2 <= 64 && p2 * m2 <= 64;
+    const int extra = (ok && o == 2) ? (ax == 0 ? n * p : ax == 1 ? m * p : m * n) : 0;
+    // per factor: columns before/after and the dropped row/column (axis order:
+    // U rows i (m) cols j (n); V rows j (n) cols k (p); W rows k (p) cols i (m))
+    const int colsU = n, colsV = p, colsW = m;
+    const int colsU2 = n2, colsV2 = p2, colsW2 = m2;
+    const int dr_u = (o == 1 && ax == 0) ? ix : -1, dc_u = (o == 1 && ax == 1) ? ix : -1;
+    const int dr_v = (o == 1 && ax == 1) ? ix : -1, dc_v = (o == 1 && ax == 2) ? ix : -1;
+    const int dr_w = (o == 1 && ax == 2) ? ix : -1, dc_w = (o == 1 && ax == 0) ? ix : -1;
+    const uint64_t *src = (which ? in.best : in.cur) + (size_t)walk * in.capacity * 6;
+    uint64_t *dst = const_cast<uint64_t *>(out.start) + (size_t)walk * out.capacity * 6;
+    int count = 0;
+    if (ok) {
+        for (int base = 0; base < rank; base += 64) {
+            const int k = base + lane;
+            uint64_t f[6] = {0, 0, 0, 0, 0, 0};
+            bool keep = false;
+            if (k < rank) {
+                f[0] = remap_mask(src[k * 6 + 0], colsU, colsU2, dr_u, dc_u);
+                f[1] = remap_mask(src[k * 6 + 1], colsU, colsU2, dr_u, dc_u);
+                f[2] = remap_mask(src[k * 6 + 2], colsV, colsV2, dr_v, dc_v);
+                f[3] = remap_mask(src[k * 6 + 3], colsV, colsV2, dr_v, dc_v);
+                f[4] = remap_mask(src[k * 6 + 4], colsW, colsW2, dr_w, dc_w);
+                f[5] = remap_mask(src[k * 6 + 5], colsW, colsW2, dr_w, dc_w);
+                keep = f[0] != 0 && f[2] != 0 && f[4] != 0;
+                if (mode == 0) {
+                    // Sec. 3.6: first non-zero of u, then of v, positive; w absorbs
+                    for (int X = 0; X < 2; ++X) {
+                        const uint64_t low = f[2 * X] & (~f[2 * X] + 1);
+                        if (f[2 * X + 1] & low) {
+                            f[2 * X + 1] ^= f[2 * X];
+                            f[5] ^= f[4];
+                        }
+                    }
+                }
+            }
+            const uint64_t mk = __ballot(keep);
+            const int pos = count + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
+            if (keep && pos < out.capacity)
+                for (int x = 0; x < 6; ++x) dst[pos * 6 + x] = f[x];
+            count += __builtin_popcountll(mk);
+        }
+        // extend: the naive scheme of the new index
+        for (int q = lane; q < extra; q += 64) {
+            int i, j, k;
+            if (ax == 2) { i = q / n; j = q % n; k = p; }
+            else if (ax == 0) { i = m; j = q / p; k = q % p; }
+            else { i = q / p; j = n; k = q % p; }
+            const int pos = count + q;
+            if (pos < out.capacity) {
+                dst[pos * 6 + 0] = 1ull << (i * n2 + j);
+                dst[pos * 6 + 1] = 0;
+                dst[pos * 6 + 2] = 1ull << (j * p2 + k);
+                dst[pos * 6 + 3] = 0;
+                dst[pos * 6 + 4] = 1ull << (k * m2 + i);
+                dst[pos * 6 + 5] = 0;
+            }
+        }
+        count += extra;
+    }
+    if (lane == 0) {
+        const bool fits = ok && count <= out.capacity;
+        ho->m = fits ? m2 : m;
+        ho->n = fits ? n2 : n;
+        ho->p = fits ? p2 : p;
+        ho->mode = mode;
+        ho->target_rank = h->target_rank;
+        ho->start_rank = fits ? count : -1;
+        const int rc = count + r_cap_extra;
+        ho->r_cap = fits ? (rc < out.capacity ? rc : out.capacity) : 0;
+    }
+}
+
 // feature rows of the proposal network from log records, one row per thread
 __global__ void __launch_bounds__(256) features_kernel(const tsf_flip_log *log, int64_t n,
                                                        uint16_t *X)
@@ -358,6 +470,27 @@ tsf_status tsf_walk_learned(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_
         a.phase = 2;
         if ((st = run(L, a, s))) return st;
     }
+    return TSF_OK;
+}
+
+tsf_status tsf_meta_batch(const tsf_walk_batch *in, int32_t which, const int32_t *op,
+                          const int32_t *axis, const int32_t *index, int32_t r_cap_extra,
+                          const tsf_walk_batch *out, void *hip_stream)
+{
+    tsf_status st = check_batch(in);
+    if (st) return st;
+    if ((st = check_batch(out))) return st;
+    if (in->n_walks != out->n_walks) return tsf_fail(TSF_E_ARG, "batches differ in n_walks");
+    if (which < 0 || which > 1) return tsf_fail(TSF_E_ARG, "which %d not in 0..1", which);
+    if (r_cap_extra < 0) return tsf_fail(TSF_E_ARG, "r_cap_extra < 0");
+    if (in->n_walks == 0) return TSF_OK;
+    if (!op || !axis || !index) return tsf_fail(TSF_E_ARG, "null op/axis/index");
+    if ((const void *)in->start == (const void *)out->start || in->cur == out->start ||
+        in->best == out->start)
+        return tsf_fail(TSF_E_ARG, "in and out must not share scheme buffers");
+    hipLaunchKernelGGL(meta_kernel, dim3(in->n_walks), dim3(64), 0, (hipStream_t)hip_stream, *in,
+                       which, op, axis, index, r_cap_extra, *out);
+    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "meta launch failed");
     return TSF_OK;
 }
 

@@ -1,0 +1,148 @@
+"""Training and evaluation of the learned flip proposal (host driver).
+
+All arithmetic runs in libtsf's kernels: the walks (with their training
+log), the feature rows, and the network's forward, backward and Adam steps.
+This module only orchestrates: it labels logged iterations, samples
+minibatches and times the comparison with uniform proposals.
+
+Label of a logged iteration t of a walk (a flip was applied): 1 if the walk's
+rank after some iteration in (t, t + window] is below its rank after t,
+else 0; iterations whose window runs past the end of the log are dropped.
+"""
+import time
+
+import numpy as np
+
+from . import tsf
+
+
+def window_min_after(x, window):
+    """m[t] = min(x[t+1 .. t+window]) per row (inf where the window is cut)."""
+    L = x.shape[-1]
+    big = np.iinfo(np.int32).max
+    shifted = np.full(x.shape, big, dtype=np.int64)
+    shifted[..., :-1] = x[..., 1:]
+    # sliding minimum of width `window` by doubling: mins of widths 1, 2, 4, ...
+    res = np.full(x.shape, big, dtype=np.int64)
+    cur = shifted.copy()
+    width, offset = 1, 0
+    w = window
+    while w:
+        if w & 1:
+            part = np.full(x.shape, big, dtype=np.int64)
+            if offset < L:
+                part[..., :L - offset] = cur[..., offset:]
+            res = np.minimum(res, part)
+            offset += width
+        nxt = np.full(x.shape, big, dtype=np.int64)
+        if width < L:
+            nxt[..., :L - width] = cur[..., width:]
+        cur = np.minimum(cur, nxt)
+        width *= 2
+        w >>= 1
+    return res
+
+
+def collect(ctx, scheme, n_walks, n_iters, r_cap, base_seed=1000, window=1000, prm=None):
+    """Run uniform walks with the training log on; returns (records tensor on
+    the GPU, int64 indices of usable records, float32 labels)."""
+    import torch
+    b = tsf.WalkBatch([(scheme, n_walks, r_cap, 0)], rec_cap=4, log_cap=n_iters)
+    b.init(ctx)
+    prm = prm or tsf.walk_params(base_seed=base_seed, max_iters=n_iters, plateau=50000)
+    b.walk(ctx, prm, n_iters)
+    torch.cuda.synchronize()
+    rec = b.log.reshape(-1, 16)
+    words = rec[:, 1].cpu().numpy()  # rank_before | rank_after << 32
+    rank_before = (words & 0xFFFFFFFF).astype(np.int64)
+    rank_before[rank_before >= 1 << 31] -= 1 << 32
+    rank_after = (words >> 32).astype(np.int64)
+    ra = rank_after.reshape(n_walks, n_iters)
+    later = window_min_after(ra, window)
+    label = (later < ra).reshape(-1)
+    usable = (rank_before >= 0).reshape(n_walks, n_iters)
+    usable[:, n_iters - window:] = False
+    idx = np.flatnonzero(usable.reshape(-1))
+    return rec, idx, label[idx].astype(np.float32)
+
+
+def train(net, rec, idx, labels, steps, batch=4096, lr=1e-3, seed=0, log_every=0):
+    """Minibatch Adam on the binary cross-entropy; returns the loss history."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dev = rec.device
+    lab = torch.from_numpy(labels).to(dev)
+    idx_d = torch.from_numpy(idx).to(dev)
+    hist = []
+    for s in range(steps):
+        pick = torch.from_numpy(rng.integers(0, idx.size, batch)).to(dev)
+        rows = rec.index_select(0, idx_d.index_select(0, pick)).contiguous()
+        X = tsf.features_from_log(rows)
+        y = lab.index_select(0, pick).contiguous()
+        h1, h2, logit = net.forward(X)
+        loss = net.backward(X, y, h1, h2, logit)
+        net.step(lr=lr)
+        if log_every and (s % log_every == 0 or s == steps - 1):
+            hist.append((s, float(loss.item())))
+    return hist
+
+
+def evaluate(net, rec, idx, labels, n=65536, seed=1):
+    """Loss and ranking quality (AUC) of the network on sampled records."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dev = rec.device
+    pick = rng.choice(idx.size, min(n, idx.size), replace=False)
+    rows = rec.index_select(0, torch.from_numpy(idx[pick]).to(dev)).contiguous()
+    X = tsf.features_from_log(rows)
+    _, _, logit = net.forward(X)
+    z = logit.cpu().numpy().astype(np.float64)
+    y = labels[pick].astype(np.float64)
+    loss = float(np.mean(np.logaddexp(0.0, z) - y * z))
+    pos, neg = z[y > 0.5], z[y < 0.5]
+    if pos.size == 0 or neg.size == 0:
+        auc = float("nan")
+    else:
+        order = np.argsort(np.concatenate([pos, neg]))
+        ranks = np.empty(order.size)
+        ranks[order] = np.arange(1, order.size + 1)
+        auc = float((ranks[:pos.size].sum() - pos.size * (pos.size + 1) / 2) / (pos.size * neg.size))
+    return {"loss": loss, "auc": auc, "positives": float(y.mean()), "n": int(y.size)}
+
+
+def time_to_ranks(ctx, scheme, n_walks, r_cap, ladder, wall_s, base_seed, net=None,
+                  iters_per_call=None, prm_kw=None):
+    """Walk n_walks walks (learned proposals when net is given, else uniform)
+    until wall_s seconds have passed; returns the wall time and the iteration at
+    which the batch's best rank first reached each rung of the ladder."""
+    import torch
+    b = tsf.WalkBatch([(scheme, n_walks, r_cap, min(ladder))], rec_cap=64)
+    b.init(ctx)
+    kw = dict(base_seed=base_seed, max_iters=10 ** 9, plateau=50000)
+    kw.update(prm_kw or {})
+    prm = tsf.walk_params(**kw)
+    ws = tsf.LearnWorkspace(n_walks) if net is not None else None
+    best_col = b.hdr.view(torch.int32).view(n_walks, 40)[:, 7]
+    iters_per_call = iters_per_call or (20 if net is not None else 2000)
+    hit_s, hit_it = {}, {}
+    done_iters = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        if net is not None:
+            b.walk_learned(ctx, prm, net, ws, iters_per_call)
+        else:
+            b.walk(ctx, prm, iters_per_call)
+        done_iters += iters_per_call
+        best = int(best_col.min().item())
+        now = time.perf_counter() - t0
+        for rank in ladder:
+            if best <= rank and rank not in hit_s:
+                hit_s[rank] = now
+                hit_it[rank] = done_iters
+        if now >= wall_s or best <= min(ladder):
+            break
+    hdr = b.headers()
+    return {"wall_s": now, "iterations": done_iters, "time_to_rank_s": hit_s,
+            "iters_to_rank": hit_it, "flips": int(hdr["counters"][:, 1].sum()),
+            "best_rank": int(hdr["best_rank"].min())}

@@ -124,6 +124,8 @@ def lib():
             ("tsf_walk_learned", [C.c_void_p, P(WalkParams), P(WalkBatchC), P(MlpC), P(LearnWsC),
                                   C.c_int64, P(Launch), C.c_void_p]),
             ("tsf_format_slot", [C.c_int32, C.c_int32, C.c_int32]),
+            ("tsf_meta_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_int32, P(WalkBatchC), C.c_void_p]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -322,6 +324,39 @@ class WalkBatch:
                                device=dev)
         self.log = (torch.zeros((self.n_walks, self.log_cap, 16), dtype=torch.int64, device=dev)
                     if self.log_cap else None)
+
+    @classmethod
+    def empty(cls, n_walks, capacity, mode, max_len, rec_cap=64, device="cuda", log_cap=0):
+        """Buffers for n_walks walks with no start schemes yet (see meta_from)."""
+        import torch
+        self = cls.__new__(cls)
+        self.torch = torch
+        self.log_cap = int(log_cap)
+        self.mode, self.n_walks, self.capacity = int(mode), int(n_walks), int(capacity)
+        self.rec_cap, self.max_len = int(rec_cap), int(max_len)
+        self.groups = []
+        dev = torch.device(device)
+        self.hdr = torch.zeros(self.n_walks * HEADER_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        self.start = torch.zeros((self.n_walks, self.capacity, 6), dtype=torch.int64, device=dev)
+        self.cur = torch.zeros_like(self.start)
+        self.best = torch.zeros_like(self.start)
+        self.rec = torch.zeros((self.n_walks, max(self.rec_cap, 1), 2), dtype=torch.int64,
+                               device=dev)
+        self.log = (torch.zeros((self.n_walks, self.log_cap, 16), dtype=torch.int64, device=dev)
+                    if self.log_cap else None)
+        return self
+
+    def meta_from(self, src, which, op, axis, index, r_cap_extra=8):
+        """Start schemes of this batch := project / extend / copy of src's
+        current (which=0) or best (which=1) schemes (tsf_meta_batch); then init."""
+        torch = self.torch
+        dev = self.hdr.device
+        op_d = torch.as_tensor(np.asarray(op, np.int32)).to(dev)
+        ax_d = torch.as_tensor(np.asarray(axis, np.int32)).to(dev)
+        ix_d = torch.as_tensor(np.asarray(index, np.int32)).to(dev)
+        check(lib().tsf_meta_batch(C.byref(src.c()), which, C.c_void_p(op_d.data_ptr()),
+                                   C.c_void_p(ax_d.data_ptr()), C.c_void_p(ix_d.data_ptr()),
+                                   r_cap_extra, C.byref(self.c()), self._stream()))
 
     def c(self):
         return WalkBatchC(self.n_walks, self.capacity, self.rec_cap, self.mode, self.max_len, 0,

@@ -145,3 +145,54 @@ def test_config2_full_batch_sampled(ctx):
     compare(b, run_oracle(groups, prm, walks, 4000), "cfg2")
     nv = b.verify_device(which=1).cpu().numpy()
     assert (nv == 0).all()
+
+
+def test_meta_project_extend_batch_then_walk(ctx):
+    """Device project/extend of walked schemes equals the oracle's project /
+    extend of its own (bit-identical) walked schemes; walks continued from the
+    new start schemes stay identical to the oracle."""
+    from oracle import pyoracle as O
+    from tests.gpu_parity import oracle_params, oracle_start
+    s = _std(3, 3, 4)
+    n = 12
+    groups = [(s, n, 44, 0)]
+    prm = tsf.walk_params(base_seed=41, max_iters=400, plateau=10 ** 6)
+    b = _run(ctx, groups, prm, 400)
+    ow = run_oracle(groups, prm, range(n), 400)
+    compare(b, ow, "before meta")
+    # per walk: project along each axis / extend along each axis / copy
+    ops = [1, 1, 1, 2, 2, 2, 0, 1, 1, 2, 1, 0]
+    axes = [0, 1, 2, 0, 1, 2, 0, 2, 2, 2, 1, 1]
+    idxs = [0, 2, 3, 0, 0, 0, 0, 0, 1, 0, 1, 0]
+    which = 0
+    out = tsf.WalkBatch.empty(n, 64, tsf.TSF_TERNARY, max_len=20, rec_cap=16)
+    out.meta_from(b, which, ops, axes, idxs, r_cap_extra=8)
+    out.init(ctx)
+    _sync()
+    hdr = out.headers()
+    starts = {}
+    for w in range(n):
+        src = ow[w].cur
+        if ops[w] == 1:
+            want = O.project(src, axes[w], idxs[w])
+        elif ops[w] == 2:
+            want = O.extend(src, axes[w])
+        else:
+            want = O.copy(src)
+        wd = O.from_c(want)
+        got = out.scheme(w, "start", hdr)
+        assert (got.m, got.n, got.p) == (wd["m"], wd["n"], wd["p"]), w
+        for a, bb in zip(got.live(), (wd["U"], wd["V"], wd["W"])):
+            assert np.array_equal(a, bb), w
+        assert hdr["done"][w] == 0 and tsf.verify(got) == 0
+        starts[w] = want
+    # continue walking from the new schemes
+    prm2 = tsf.walk_params(base_seed=77, max_iters=300, plateau=10 ** 6, t_expand=1 << 28)
+    out.walk(ctx, prm2, 300, 0, 0, 2)
+    _sync()
+    want_walks = {}
+    for w in range(n):
+        o = O.new_walk(starts[w])
+        O.run(o, oracle_params(prm2, w, int(hdr["r_cap"][w]), 0), 300)
+        want_walks[w] = o
+    compare(out, want_walks, "after meta")
