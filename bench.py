@@ -69,6 +69,62 @@ def cpu_baseline(n_walks=256, iters=100000, threads=None):
                                                           its / dt)}
 
 
+def learned_vs_uniform(ctx, args):
+    """Train the proposal network on logged uniform (3,3,3) walks, then compare
+    learned and uniform proposals at equal wall time on R runs over disjoint
+    seed blocks: medians of the time and of the iterations to each rank."""
+    import torch
+    from paper_2511_20317_amd import learn, tsf
+    s333 = tsf.init_scheme(3, 3, 3)
+    t0 = time.perf_counter()
+    rec, idx, lab = learn.collect(ctx, s333, args.learn_walks, args.learn_iters, 35,
+                                  base_seed=10 ** 7)
+    t_collect = time.perf_counter() - t0
+    net = tsf.Mlp()
+    rng = np.random.default_rng(0)
+    net.set_params(rng.standard_normal((512, 256)) * np.sqrt(2 / 64), np.zeros(256),
+                   rng.standard_normal((256, 256)) * np.sqrt(2 / 256), np.zeros(256),
+                   rng.standard_normal(256) * np.sqrt(1 / 256), np.zeros(1))
+    ev0 = learn.evaluate(net, rec, idx, lab)
+    t0 = time.perf_counter()
+    hist = learn.train(net, rec, idx, lab, args.learn_steps, batch=4096, lr=1e-3,
+                       log_every=max(args.learn_steps // 5, 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ev = learn.evaluate(net, rec, idx, lab)
+    del rec
+    out = {"train": {"logged_iterations": int(idx.size), "positive_rate": float(lab.mean()),
+                     "collect_s": t_collect, "train_s": t_train, "steps": args.learn_steps,
+                     "batch": 4096, "loss_history": hist, "eval_before": ev0, "eval_after": ev}}
+    results = {}
+    for fmt, r_cap, ladder in [((3, 3, 3), 35, (26, 25, 24, 23)), ((4, 4, 4), 64, (63, 62, 61, 60))]:
+        s = tsf.init_scheme(*fmt)
+        runs = {"uniform": [], "learned": []}
+        for rep in range(args.ab_runs):
+            seed = 2 ** 20 * (rep + 1)
+            for mode in ("uniform", "learned"):
+                res = learn.time_to_ranks(ctx, s, args.ab_walks, r_cap, ladder, args.ab_seconds,
+                                          seed, net=net if mode == "learned" else None)
+                runs[mode].append(res)
+                print("%s %s run %d: best %d, %.2f s, %d iterations" %
+                      (fmt, mode, rep, res["best_rank"], res["wall_s"], res["iterations"]),
+                      file=sys.stderr, flush=True)
+        summ = {}
+        for mode, rs in runs.items():
+            summ[mode] = {
+                "median_time_to_rank_s": {str(k): float(np.median([r["time_to_rank_s"].get(k, np.inf)
+                                                                  for r in rs])) for k in ladder},
+                "median_iters_to_rank": {str(k): float(np.median([r["iters_to_rank"].get(k, np.inf)
+                                                                 for r in rs])) for k in ladder},
+                "iterations_per_s": float(np.median([r["iterations"] / r["wall_s"] for r in rs])),
+                "best_rank_median": float(np.median([r["best_rank"] for r in rs])),
+            }
+        results["%d,%d,%d" % fmt] = summ
+    out["ab"] = results
+    out["ab_setup"] = {"runs": args.ab_runs, "walks": args.ab_walks, "wall_s": args.ab_seconds}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +141,14 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=100000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter scale)")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the proposal network and compare it with uniform proposals")
+    ap.add_argument("--learn-walks", type=int, default=2048)
+    ap.add_argument("--learn-iters", type=int, default=6000)
+    ap.add_argument("--learn-steps", type=int, default=2000)
+    ap.add_argument("--ab-runs", type=int, default=9)
+    ap.add_argument("--ab-walks", type=int, default=4096)
+    ap.add_argument("--ab-seconds", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the walks shard by walk id with no "
@@ -187,6 +251,8 @@ def main():
         "best_schemes_failing_brent": bad_total,
         "learned_vs_uniform": None,
     }
+    if args.learned:
+        out["learned_vs_uniform"] = learned_vs_uniform(ctx, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_walks, args.cpu_iters)
     print(json.dumps(out))
