@@ -279,9 +279,21 @@ tsf_status check_batch(const tsf_walk_batch *b)
 
 }  // namespace
 
+// A captured sequence of learned iterations, replayed with hipGraphLaunch.
+struct GraphEntry {
+    unsigned char key[sizeof(KArgs) + 8 * sizeof(void *)];
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int64_t chunk;
+    bool used;
+};
+
 struct tsf_ctx {
     int device;
     int cu_count;
+    hipStream_t capture;      // private stream used only to capture graphs
+    GraphEntry graphs[8];
+    int next_graph;
 };
 
 extern "C" {
@@ -295,14 +307,26 @@ tsf_status tsf_ctx_create(tsf_ctx **ctx)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return tsf_fail(TSF_E_DEVICE, "hipDeviceGetAttribute failed");
     tsf_ctx *c = new tsf_ctx;
+    std::memset(c, 0, sizeof *c);
     c->device = dev;
     c->cu_count = cus;
+    if (hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return tsf_fail(TSF_E_DEVICE, "cannot create the capture stream");
+    }
     *ctx = c;
     return TSF_OK;
 }
 
 tsf_status tsf_ctx_destroy(tsf_ctx *ctx)
 {
+    if (!ctx) return TSF_OK;
+    for (GraphEntry &g : ctx->graphs)
+        if (g.used) {
+            hipGraphExecDestroy(g.exec);
+            hipGraphDestroy(g.graph);
+        }
+    if (ctx->capture) hipStreamDestroy(ctx->capture);
     delete ctx;
     return TSF_OK;
 }
@@ -462,14 +486,68 @@ tsf_status tsf_walk_learned(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_
     a.choice_cap = ws->choice ? ws->choice_cap : 0;
     a.n_iters = 1;
     hipStream_t s = (hipStream_t)hip_stream;
-    for (int64_t it = 0; it < n_iters; ++it) {
+    // one learned iteration: propose, score, apply
+    auto iteration = [&](hipStream_t on) -> tsf_status {
+        tsf_status e;
         a.phase = 1;
-        if ((st = run(L, a, s))) return st;
-        if ((st = tsf_mlp_fwd(net, ws->feat, (int32_t)rows, ws->h1, ws->h2, ws->logit, hip_stream)))
-            return st;
+        if ((e = run(L, a, on))) return e;
+        if ((e = tsf_mlp_fwd(net, ws->feat, (int32_t)rows, ws->h1, ws->h2, ws->logit, on)))
+            return e;
         a.phase = 2;
-        if ((st = run(L, a, s))) return st;
+        return run(L, a, on);
+    };
+    // Every iteration launches the same kernels with the same arguments (the
+    // walk state lives in device memory), so a chunk of iterations is
+    // captured once into a HIP graph and replayed.
+    const int64_t chunk = 16;
+    if (!ctx || n_iters < chunk) {
+        for (int64_t it = 0; it < n_iters; ++it)
+            if ((st = iteration(s))) return st;
+        return TSF_OK;
     }
+    unsigned char key[sizeof(GraphEntry::key)];
+    std::memset(key, 0, sizeof key);
+    a.phase = 0;
+    std::memcpy(key, &a, sizeof a);
+    const void *ptrs[8] = {net->param, net->wbf, ws->cand, ws->feat, ws->h1, ws->h2, ws->logit,
+                           (const void *)L.fn};
+    std::memcpy(key + sizeof a, ptrs, sizeof ptrs);
+    GraphEntry *ge = nullptr;
+    for (GraphEntry &g : ctx->graphs)
+        if (g.used && g.chunk == chunk && std::memcmp(g.key, key, sizeof key) == 0) ge = &g;
+    if (!ge) {
+        ge = &ctx->graphs[ctx->next_graph];
+        ctx->next_graph = (ctx->next_graph + 1) % 8;
+        if (ge->used) {
+            hipGraphExecDestroy(ge->exec);
+            hipGraphDestroy(ge->graph);
+            ge->used = false;
+        }
+        if (hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return tsf_fail(TSF_E_DEVICE, "stream capture failed to start");
+        for (int64_t it = 0; it < chunk; ++it)
+            if ((st = iteration(ctx->capture))) {
+                hipGraph_t dummy;
+                hipStreamEndCapture(ctx->capture, &dummy);
+                if (dummy) hipGraphDestroy(dummy);
+                return st;
+            }
+        if (hipStreamEndCapture(ctx->capture, &ge->graph) != hipSuccess)
+            return tsf_fail(TSF_E_DEVICE, "stream capture failed");
+        if (hipGraphInstantiate(&ge->exec, ge->graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(ge->graph);
+            return tsf_fail(TSF_E_DEVICE, "graph instantiation failed");
+        }
+        std::memcpy(ge->key, key, sizeof key);
+        ge->chunk = chunk;
+        ge->used = true;
+    }
+    int64_t done = 0;
+    for (; done + chunk <= n_iters; done += chunk)
+        if (hipGraphLaunch(ge->exec, s) != hipSuccess)
+            return tsf_fail(TSF_E_DEVICE, "graph launch failed");
+    for (; done < n_iters; ++done)
+        if ((st = iteration(s))) return st;
     return TSF_OK;
 }
 
