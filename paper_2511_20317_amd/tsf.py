@@ -94,6 +94,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libtsf.so is not built (run paper_2511_20317_amd/build.py); "
                               "there is no fallback implementation")
+        # torch ships its own HIP runtime; loading it first lets libtsf bind to
+        # that same runtime instead of pulling a second copy into the process
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.POINTER
         L.tsf_last_error.restype = C.c_char_p
