@@ -5,10 +5,11 @@
 //   logit = h2 . w3 + b3;  loss = mean(softplus(logit) - y logit)
 //
 // The three dense products of the forward pass and the three of the backward
-// pass run through one tiled GEMM kernel (64x64 output tile per workgroup,
-// four wavefronts of 32x32, K staged through LDS 32 at a time) with fused
-// epilogues: bias + ReLU + bf16 rounding (forward), ReLU mask + bf16
-// rounding (backpropagated deltas), plain fp32 (weight gradients).
+// pass run through one tiled GEMM kernel (128x128 output tile per workgroup,
+// four wavefronts of 64x64 on v_mfma_f32_32x32x16_bf16, K staged through LDS
+// 32 at a time) with fused epilogues: bias + ReLU + bf16 rounding (forward),
+// ReLU mask + bf16 rounding (backpropagated deltas), plain fp32 (weight
+// gradients).
 #include <hip/hip_runtime.h>
 
 #include "../../include/tsf.h"
@@ -18,7 +19,6 @@
 
 namespace {
 
-typedef short v4i16 __attribute__((ext_vector_type(4)));
 typedef float v16f32 __attribute__((ext_vector_type(16)));
 
 constexpr int IN = TSF_MLP_IN, HID = TSF_MLP_HID;
@@ -63,20 +63,38 @@ struct GemmArgs {
     float *out_f32;         // M x N row-major
 };
 
-constexpr int BM = 64, BN = 64, BK = 32;
+typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 
-// Stage a BM x BK tile of operand (rows r0.., cols k0..) into LDS as
-// tile[r][k] (k fastest), zero outside the matrix.  Threads walk the
-// operand's contiguous dimension so that global reads coalesce.
-__device__ __forceinline__ void stage(uint16_t (*tile)[BK + 8], const uint16_t *P, int64_t s_row,
+// Output tile 128 x 128 per workgroup of four wavefronts (2 x 2 of 64 x 64);
+// K is staged through LDS 32 at a time.
+constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+
+// Stage a 128 x BK tile of an operand (rows r0.., cols k0..) into LDS as
+// tile[r][k], zero outside the matrix.  When the operand's k is contiguous,
+// each thread moves 8 consecutive elements (16 bytes) at a time; otherwise
+// threads walk the contiguous row dimension so reads still coalesce.
+__device__ __forceinline__ void stage(uint16_t (*tile)[LDK], const uint16_t *P, int64_t s_row,
                                       int64_t s_col, int rows, int K, int r0, int k0)
 {
     const int tid = threadIdx.x;
     if (s_col == 1) {
-        for (int e = tid; e < BM * BK; e += 256) {
-            const int r = e / BK, k = e % BK;
-            const int gr = r0 + r, gk = k0 + k;
-            tile[r][k] = (gr < rows && gk < K) ? P[gr * s_row + gk] : (uint16_t)0;
+        for (int e = tid; e < BM * BK / 8; e += 256) {
+            const int r = e / (BK / 8), kc = (e % (BK / 8)) * 8;
+            const int gr = r0 + r, gk = k0 + kc;
+            const uint16_t *src = P + gr * s_row + gk;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gr < rows) {
+                if (gk + 8 <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+                    v = *reinterpret_cast<const uint4 *>(src);
+                } else {
+                    uint16_t tmp[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) tmp[q] = (gk + q < K) ? src[q] : (uint16_t)0;
+                    v = make_uint4(tmp[0] | (uint32_t)tmp[1] << 16, tmp[2] | (uint32_t)tmp[3] << 16,
+                                   tmp[4] | (uint32_t)tmp[5] << 16, tmp[6] | (uint32_t)tmp[7] << 16);
+                }
+            }
+            *reinterpret_cast<uint4 *>(&tile[r][kc]) = v;
         }
     } else {
         for (int e = tid; e < BM * BK; e += 256) {
@@ -89,50 +107,64 @@ __device__ __forceinline__ void stage(uint16_t (*tile)[BK + 8], const uint16_t *
 
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 {
-    __shared__ uint16_t As[BM][BK + 8];
-    __shared__ uint16_t Bs[BN][BK + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDK];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // this wave's 32x32 sub-tile
-    v16f32 acc;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // this wave's 64x64 sub-tile
+    v16f32 acc[2][2];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[a][b][q] = 0.0f;
+    const int row = lane & 31, kh = 8 * (lane >> 5);
     for (int k0 = 0; k0 < g.K; k0 += BK) {
         stage(As, g.A, g.a_row, g.a_col, g.M, g.K, m0, k0);
         stage(Bs, g.B, g.b_row, g.b_col, g.N, g.K, n0, k0);
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 8) {
-            // 32x32x8: lane l holds A[l%32][4*(l/32) + 0..3] and B[l%32][same k]
-            const int row = lane & 31, kq = kk + 4 * (lane >> 5);
-            v4i16 av, bv;
+        for (int kk = 0; kk < BK; kk += 16) {
+            // 32x32x16: lane l holds A[l%32][8*(l/32) + 0..7] and B[l%32][same k]
+            v8bf16 av[2], bv[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                av[q] = (short)As[wm + row][kq + q];
-                bv[q] = (short)Bs[wn + row][kq + q];
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+            for (int a = 0; a < 2; ++a)
+                av[a] = *reinterpret_cast<const v8bf16 *>(&As[wm + 32 * a + row][kk + kh]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                bv[b] = *reinterpret_cast<const v8bf16 *>(&Bs[wn + 32 * b + row][kk + kh]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
     }
     // accumulator register q of lane l: row 8*(q/4) + 4*(l/32) + q%4, column l%32
-    const int col = n0 + wn + (lane & 31);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int row = m0 + wm + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-        if (row >= g.M || col >= g.N) continue;
-        float v = acc[q];
-        const int64_t o = (int64_t)row * g.N + col;
-        if (g.ep == EP_BIAS_RELU_BF16) {
-            v += g.bias[col];
-            g.out_bf16[o] = to_bf16(v > 0.0f ? v : 0.0f);
-        } else if (g.ep == EP_MASK_BF16) {
-            const bool keep = from_bf16(g.mask[o]) > 0.0f;
-            g.out_bf16[o] = to_bf16(keep ? v : 0.0f);
-        } else {
-            g.out_f32[o] = v;
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int col = n0 + wn + 32 * b + (lane & 31);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int rr = m0 + wm + 32 * a + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                if (rr >= g.M || col >= g.N) continue;
+                float v = acc[a][b][q];
+                const int64_t o = (int64_t)rr * g.N + col;
+                if (g.ep == EP_BIAS_RELU_BF16) {
+                    v += g.bias[col];
+                    g.out_bf16[o] = to_bf16(v > 0.0f ? v : 0.0f);
+                } else if (g.ep == EP_MASK_BF16) {
+                    const bool keep = from_bf16(g.mask[o]) > 0.0f;
+                    g.out_bf16[o] = to_bf16(keep ? v : 0.0f);
+                } else {
+                    g.out_f32[o] = v;
+                }
+            }
         }
-    }
 }
 
 // logit = h2 . w3 + b3; one wavefront per row
@@ -171,19 +203,20 @@ __global__ void __launch_bounds__(256) delta_kernel(const float *logit, const fl
     }
 }
 
-// column sums: out[n] = sum_m A[m][n] (bf16 A), and the weighted sum
-// out[n] = sum_m w[m] A[m][n] when w is given
+// column sums: out[n] += sum over this block's rows of A[m][n] (bf16 A), or
+// of w[m] A[m][n] when w is given; out must be zeroed first
 __global__ void __launch_bounds__(256) colsum_kernel(const uint16_t *A, const float *w, int M,
                                                      int N, float *out)
 {
     const int n = blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
+    const int m_begin = blockIdx.y * 64, m_end = min(M, m_begin + 64);
     float s = 0.0f;
-    for (int m = 0; m < M; ++m) {
+    for (int m = m_begin; m < m_end; ++m) {
         const float a = from_bf16(A[(int64_t)m * N + n]);
         s += w ? w[m] * a : a;
     }
-    out[n] = s;
+    atomicAdd(&out[n], s);
 }
 
 __global__ void sum_kernel(const float *v, int M, float *out)
@@ -302,9 +335,12 @@ tsf_status tsf_mlp_bwd(const tsf_mlp *net, const uint16_t *X, const float *y, in
     hipLaunchKernelGGL(delta_kernel, dim3((M + 3) / 4), dim3(256), 0, s, logit, y, h2,
                        net->wbf + Q_W3, M, d3, d2, loss);
     // dW3 = h2^T d3, db3 = sum d3, db2 = colsum d2
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, h2, d3, M, HID, gp + O_W3);
+    const dim3 cs_grid(1, (M + 63) / 64);
+    hipLaunchKernelGGL(zero_kernel, dim3((TSF_MLP_NPARAM + 255) / 256), dim3(256), 0, s, gp,
+                       TSF_MLP_NPARAM);
+    hipLaunchKernelGGL(colsum_kernel, cs_grid, dim3(256), 0, s, h2, d3, M, HID, gp + O_W3);
     hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, d3, M, gp + O_B3);
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, d2, (const float *)nullptr, M, HID,
+    hipLaunchKernelGGL(colsum_kernel, cs_grid, dim3(256), 0, s, d2, (const float *)nullptr, M, HID,
                        gp + O_B2);
     GemmArgs g;
     std::memset(&g, 0, sizeof g);
@@ -320,7 +356,7 @@ tsf_status tsf_mlp_bwd(const tsf_mlp *net, const uint16_t *X, const float *y, in
     g.M = M; g.N = HID; g.K = HID;
     g.ep = EP_MASK_BF16; g.mask = h1; g.out_bf16 = d1; g.out_f32 = nullptr;
     if ((st = launch_gemm(g, s))) return st;
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, d1, (const float *)nullptr, M, HID,
+    hipLaunchKernelGGL(colsum_kernel, cs_grid, dim3(256), 0, s, d1, (const float *)nullptr, M, HID,
                        gp + O_B1);
     // dW1^T[n][k] = sum_m d1[m][n] X[m][k]
     g.A = d1; g.a_row = 1; g.a_col = HID;
