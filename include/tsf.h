@@ -236,6 +236,18 @@ typedef struct tsf_ctx tsf_ctx;
 tsf_status tsf_ctx_create(tsf_ctx **ctx);
 tsf_status tsf_ctx_destroy(tsf_ctx *ctx);
 
+/* Autotuner: time every launch configuration that fits the batch (strategy,
+ * lanes per walk, wavefronts per workgroup) for trial_iters iterations on a
+ * private copy of the batch's state -- the batch itself is not changed -- and
+ * remember the fastest for batches of the same capacity, max_len, mode and
+ * size class; later tsf_walk calls with launch == NULL (or all fields 0) use
+ * it.  The choice is also written to *chosen (may be NULL).  Results of walks
+ * never depend on the configuration.  Synchronous.  The copy is allocated
+ * inside the context and kept until tsf_ctx_destroy.
+ * Errors: TSF_E_ARG, TSF_E_CAPACITY, TSF_E_DEVICE. */
+tsf_status tsf_autotune(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                        int64_t trial_iters, tsf_launch *chosen, void *hip_stream);
+
 /* Initialise every walk of the batch from its start scheme (device kernel):
  * cur := start, best := start, counters and records cleared.  Before the
  * call the caller fills, per walk, hdr[w].{m,n,p,mode,r_cap,target_rank,

@@ -5,6 +5,7 @@
 #include "tsf_internal.h"
 
 #include <cstring>
+#include <vector>
 
 namespace tsfk {
 KernelFn pick_kernel_w0_z0(int g, int s, bool ap);
@@ -288,13 +289,52 @@ struct GraphEntry {
     bool used;
 };
 
+// A tuned launch configuration for batches of one shape.
+struct TuneEntry {
+    int32_t capacity, max_len, mode, size_class;
+    tsf_launch launch;
+    bool used;
+};
+
 struct tsf_ctx {
     int device;
     int cu_count;
     hipStream_t capture;      // private stream used only to capture graphs
     GraphEntry graphs[8];
     int next_graph;
+    TuneEntry tuned[16];
+    int next_tuned;
+    void *scratch;            // autotuner's copy of a batch
+    size_t scratch_bytes;
 };
+
+namespace {
+int size_class(int n_walks)
+{
+    int c = 0;
+    while (n_walks > 1 && c < 30) {
+        n_walks >>= 1;
+        ++c;
+    }
+    return c;
+}
+
+const tsf_launch *tuned_launch(const tsf_ctx *ctx, const tsf_walk_batch *b)
+{
+    if (!ctx) return nullptr;
+    const int sc = size_class(b->n_walks);
+    for (const TuneEntry &e : ctx->tuned)
+        if (e.used && e.capacity == b->capacity && e.max_len == b->max_len && e.mode == b->mode &&
+            e.size_class == sc)
+            return &e.launch;
+    return nullptr;
+}
+
+bool launch_is_default(const tsf_launch *l)
+{
+    return !l || (l->lanes_per_walk == 0 && l->waves_per_block == 0 && l->strategy == 0);
+}
+}  // namespace
 
 extern "C" {
 
@@ -327,6 +367,7 @@ tsf_status tsf_ctx_destroy(tsf_ctx *ctx)
             hipGraphDestroy(g.graph);
         }
     if (ctx->capture) hipStreamDestroy(ctx->capture);
+    if (ctx->scratch) hipFree(ctx->scratch);
     delete ctx;
     return TSF_OK;
 }
@@ -447,13 +488,104 @@ extern "C" {
 tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
                     int64_t n_iters, const tsf_launch *launch, void *hip_stream)
 {
-    (void)ctx;
+    if (launch_is_default(launch) && b) {
+        const tsf_launch *t = tuned_launch(ctx, b);
+        if (t) launch = t;
+    }
     KArgs a;
     Launch L;
     tsf_status st = prepare_walk(prm, b, n_iters, launch, a, L);
     if (st) return st;
     if (b->n_walks == 0 || n_iters == 0) return TSF_OK;
     return run(L, a, (hipStream_t)hip_stream);
+}
+
+tsf_status tsf_autotune(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                        int64_t trial_iters, tsf_launch *chosen, void *hip_stream)
+{
+    if (!ctx) return tsf_fail(TSF_E_ARG, "null context");
+    tsf_status st = check_batch(b);
+    if (st) return st;
+    if (!prm || trial_iters < 1) return tsf_fail(TSF_E_ARG, "bad params or trial_iters");
+    if (b->n_walks == 0) return tsf_fail(TSF_E_ARG, "empty batch");
+    const size_t n = (size_t)b->n_walks;
+    const size_t sz_hdr = n * sizeof(tsf_walk_header);
+    const size_t sz_sch = n * (size_t)b->capacity * 6 * sizeof(uint64_t);
+    const size_t sz_rec = n * (size_t)(b->rec_cap > 0 ? b->rec_cap : 1) * sizeof(tsf_record);
+    const size_t need = 2 * (sz_hdr + 2 * sz_sch + sz_rec);
+    if (ctx->scratch_bytes < need) {
+        if (ctx->scratch) hipFree(ctx->scratch);
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+        if (hipMalloc(&ctx->scratch, need) != hipSuccess)
+            return tsf_fail(TSF_E_DEVICE, "cannot allocate %zu bytes for the autotuner", need);
+        ctx->scratch_bytes = need;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    // snapshot of the batch (first half of the scratch) and the trial copy
+    unsigned char *base = (unsigned char *)ctx->scratch;
+    unsigned char *snap = base, *trial = base + need / 2;
+    auto lay = [&](unsigned char *p, tsf_walk_batch &c) {
+        c = *b;
+        c.hdr = (tsf_walk_header *)p;
+        c.cur = (uint64_t *)(p + sz_hdr);
+        c.best = (uint64_t *)(p + sz_hdr + sz_sch);
+        c.rec = (tsf_record *)(p + sz_hdr + 2 * sz_sch);
+        c.log = nullptr;
+        c.log_cap = 0;
+    };
+    tsf_walk_batch bs, bt;
+    lay(snap, bs);
+    lay(trial, bt);
+    bool ok = hipMemcpyAsync(bs.hdr, b->hdr, sz_hdr, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(bs.cur, b->cur, sz_sch, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(bs.best, b->best, sz_sch, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    if (!ok) return tsf_fail(TSF_E_DEVICE, "autotuner snapshot failed");
+    std::vector<tsf_launch> cands;
+    for (int wpb : {1, 2, 4}) {
+        if (b->capacity <= 64)
+            for (int g : {8, 16}) cands.push_back(tsf_launch{g, wpb, 1});
+        for (int g : {16, 32, 64}) cands.push_back(tsf_launch{g, wpb, 2});
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best_ms = -1.0f;
+    tsf_launch best{0, 0, 0};
+    for (const tsf_launch &c : cands) {
+        KArgs a;
+        Launch L;
+        if (prepare_walk(prm, &bt, trial_iters, &c, a, L) != TSF_OK) continue;
+        hipMemcpyAsync(bt.hdr, bs.hdr, sz_hdr, hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(bt.cur, bs.cur, sz_sch, hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(bt.best, bs.best, sz_sch, hipMemcpyDeviceToDevice, s);
+        hipEventRecord(e0, s);
+        if (run(L, a, s) != TSF_OK) continue;
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (best_ms < 0.0f) return tsf_fail(TSF_E_CAPACITY, "no launch configuration fits the batch");
+    TuneEntry *slot = nullptr;
+    const int sc = size_class(b->n_walks);
+    for (TuneEntry &e : ctx->tuned)
+        if (e.used && e.capacity == b->capacity && e.max_len == b->max_len && e.mode == b->mode &&
+            e.size_class == sc)
+            slot = &e;
+    if (!slot) {
+        slot = &ctx->tuned[ctx->next_tuned];
+        ctx->next_tuned = (ctx->next_tuned + 1) % 16;
+    }
+    *slot = TuneEntry{b->capacity, b->max_len, b->mode, sc, best, true};
+    if (chosen) *chosen = best;
+    return TSF_OK;
 }
 
 tsf_status tsf_walk_learned(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,

@@ -115,6 +115,8 @@ def lib():
             ("tsf_ctx_create", [P(C.c_void_p)]),
             ("tsf_ctx_destroy", [C.c_void_p]),
             ("tsf_walk_init", [C.c_void_p, P(WalkBatchC), C.c_void_p]),
+            ("tsf_autotune", [C.c_void_p, P(WalkParams), P(WalkBatchC), C.c_int64, P(Launch),
+                              C.c_void_p]),
             ("tsf_walk", [C.c_void_p, P(WalkParams), P(WalkBatchC), C.c_int64, P(Launch),
                           C.c_void_p]),
             ("tsf_verify_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p]),
@@ -382,6 +384,14 @@ class WalkBatch:
         la = Launch(lanes_per_walk, waves_per_block, strategy)
         check(lib().tsf_walk(ctx.ptr, C.byref(prm), C.byref(self.c()), int(n_iters),
                              C.byref(la), self._stream()))
+
+    def autotune(self, ctx: Context, prm: WalkParams, trial_iters=200):
+        """Time every launch configuration on a copy of the state; returns the
+        chosen (lanes_per_walk, waves_per_block, strategy)."""
+        la = Launch()
+        check(lib().tsf_autotune(ctx.ptr, C.byref(prm), C.byref(self.c()), int(trial_iters),
+                                 C.byref(la), self._stream()))
+        return la.lanes_per_walk, la.waves_per_block, la.strategy
 
     def walk_learned(self, ctx: Context, prm: WalkParams, net, ws, n_iters: int,
                      lanes_per_walk=0, waves_per_block=0):

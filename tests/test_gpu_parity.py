@@ -196,3 +196,22 @@ def test_meta_project_extend_batch_then_walk(ctx):
         O.run(o, oracle_params(prm2, w, int(hdr["r_cap"][w]), 0), 300)
         want_walks[w] = o
     compare(out, want_walks, "after meta")
+
+
+def test_autotune_leaves_state_and_keeps_parity(ctx):
+    """The autotuner trials run on a copy: the batch is unchanged, and walks run
+    afterwards with the tuned configuration still match the oracle."""
+    groups = [(_std(3, 3, 3), 256, 35, 23), (_std(2, 3, 4), 256, 32, 0)]
+    prm = tsf.walk_params(base_seed=123, max_iters=3000, plateau=1000)
+    b = tsf.WalkBatch(groups, rec_cap=16)
+    b.init(ctx)
+    b.walk(ctx, prm, 500)
+    _sync()
+    before = (b.hdr.clone(), b.cur.clone(), b.best.clone())
+    chosen = b.autotune(ctx, prm, trial_iters=300)
+    _sync()
+    assert chosen[0] in (8, 16, 32, 64) and chosen[2] in (1, 2)
+    assert all((x == y).all() for x, y in zip(before, (b.hdr, b.cur, b.best)))
+    b.walk(ctx, prm, 2500)  # default launch -> the tuned configuration
+    _sync()
+    compare(b, run_oracle(groups, prm, range(0, 512, 7), 3000), "autotuned")
