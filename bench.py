@@ -125,6 +125,112 @@ def learned_vs_uniform(ctx, args):
     return out
 
 
+def run_mixed(ctx, args):
+    """Mixed formats in one launch: 131,072 walks as four blocks of 32,768 over
+    (3,3,4), (3,4,5), (4,4,4), (4,4,5) from their standard schemes, r_cap =
+    r0 + 8; the same batch walked with ternary and with Z2 coefficients."""
+    import torch
+    from paper_2511_20317_amd import tsf
+    fmts = [(3, 3, 4), (3, 4, 5), (4, 4, 4), (4, 4, 5)]
+    per = args.walks // 4
+    out = {}
+    for mode, name in ((tsf.TSF_TERNARY, "ternary"), (tsf.TSF_Z2, "z2")):
+        groups = [(tsf.init_scheme(*f, mode=mode), per, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
+        b = tsf.WalkBatch(groups, rec_cap=64)
+        prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
+        b.init(ctx)
+        tuned = b.autotune(ctx, prm, trial_iters=200)
+        b.init(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        kms = 0.0
+        for k in range(args.steps):
+            ev0.record()
+            b.walk(ctx, prm, args.iters)
+            ev1.record()
+            ev1.synchronize()
+            kms += ev0.elapsed_time(ev1)
+            print("%s step %d/%d: %.2f s" % (name, k + 1, args.steps, time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        nv = b.verify_device(1)
+        hdr = b.headers()
+        best = {}
+        for (w0, nw, fmt, _, _) in b.groups:
+            br = hdr["best_rank"][w0:w0 + nw]
+            best["%d,%d,%d" % fmt] = {"best": int(br.min()), "median": float(np.median(br))}
+        flips = int(hdr["counters"][:, 1].sum())
+        out[name] = {"flips_per_s": flips / wall, "walk_kernel_ms": kms, "wall_s": wall,
+                     "launch": {"lanes_per_walk": tuned[0], "waves_per_block": tuned[1],
+                                "strategy": tuned[2]},
+                     "best_rank": best, "best_schemes_failing_brent": int((nv != 0).sum().item())}
+    return out
+
+
+def run_large(ctx, args):
+    """Large formats (4,5,12), (5,6,10), (6,7,9), 32,768 walks each from the
+    standard schemes (64-bit masks): a round in the format, a device project to
+    (m,n,p-1) and a round there, a device extend back to (m,n,p) and a round."""
+    import torch
+    from paper_2511_20317_amd import tsf
+    fmts = [(4, 5, 12), (5, 6, 10), (6, 7, 9)]
+    per = args.walks // 3
+    groups = [(tsf.init_scheme(*f), per, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
+    # room for the extend: a projected scheme has at most r0 terms and the
+    # extend along p appends m*n, and the walk there may expand 8 more
+    cap = max(f[0] * f[1] * f[2] + f[0] * f[1] + 8 for f in fmts)
+    b = tsf.WalkBatch(groups, capacity=cap, rec_cap=32)
+    prm = tsf.walk_params(base_seed=0, max_iters=10 ** 9, plateau=50000)
+    b.init(ctx)
+    n = b.n_walks
+    rng = np.random.default_rng(5)
+    flips = 0
+    kms = 0.0
+    phases = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def walk_phase(batch, label):
+        nonlocal flips, kms
+        h0 = batch.headers()["counters"][:, 1].sum()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            batch.walk(ctx, prm, args.iters, 64, 1, 2)
+        e1.record()
+        e1.synchronize()
+        kms += e0.elapsed_time(e1)
+        hdr = batch.headers()
+        flips += int(hdr["counters"][:, 1].sum() - h0)
+        res = {}
+        for q, f in enumerate(fmts):
+            sl = slice(q * per, (q + 1) * per)
+            fm = (int(hdr["m"][sl][0]), int(hdr["n"][sl][0]), int(hdr["p"][sl][0]))
+            res["%d,%d,%d" % fm] = {"best": int(hdr["best_rank"][sl].min()),
+                                    "start_median": float(np.median(hdr["start_rank"][sl]))}
+        nv = batch.verify_device(1)
+        res["failing_brent"] = int((nv != 0).sum().item())
+        phases[label] = res
+        print("phase %s done: %.1f s" % (label, time.perf_counter() - t0), file=sys.stderr,
+              flush=True)
+
+    walk_phase(b, "start")
+    small = tsf.WalkBatch.empty(n, cap, tsf.TSF_TERNARY, max_len=63, rec_cap=32)
+    idx = np.concatenate([rng.integers(0, f[2], per) for f in fmts])
+    small.meta_from(b, 1, np.ones(n), np.full(n, 2), idx, r_cap_extra=8)
+    small.init(ctx)
+    walk_phase(small, "projected")
+    back = tsf.WalkBatch.empty(n, cap, tsf.TSF_TERNARY, max_len=63, rec_cap=32)
+    back.meta_from(small, 1, np.full(n, 2), np.full(n, 2), np.zeros(n), r_cap_extra=8)
+    back.init(ctx)
+    hb = back.headers()
+    walk_phase(back, "extended")
+    wall = time.perf_counter() - t0
+    return {"flips_per_s": flips / wall, "walk_kernel_ms": kms, "wall_s": wall,
+            "phases": phases, "invalid_after_meta": int((hb["done"] < 0).sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +247,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=100000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter scale)")
+    ap.add_argument("--workload", default="333", choices=["333", "mixed", "large"],
+                    help="333: the (3,3,3) benchmark; mixed / large: the other workloads")
     ap.add_argument("--learned", action="store_true",
                     help="also train the proposal network and compare it with uniform proposals")
     ap.add_argument("--learn-walks", type=int, default=2048)
@@ -161,6 +269,24 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     ctx = tsf.Context()
+    if args.workload != "333":
+        res = run_mixed(ctx, args) if args.workload == "mixed" else run_large(ctx, args)
+        if args.workload == "mixed":
+            value = res["ternary"]["flips_per_s"]
+            desc = ("131,072 walks over (3,3,4), (3,4,5), (4,4,4), (4,4,5) in one launch, "
+                    "ternary then Z2")
+        else:
+            value = res["flips_per_s"]
+            desc = ("98,304 walks over (4,5,12), (5,6,10), (6,7,9) with device project to "
+                    "p-1 and extend back between rounds")
+        out = {"metric": "flips/sec on 1 GPU", "value": value, "unit": "flips/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": 0, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "u32" if args.workload == "mixed" else "u64",
+               "data": "synthetic", "config": {"workload": desc, "walks": args.walks,
+                                               "iters_per_step": args.iters},
+               "results": res}
+        print(json.dumps(out))
+        return
     target = 23
     groups = [(tsf.init_scheme(3, 3, 3), args.walks, 35, target)]
     prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
