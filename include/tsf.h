@@ -220,10 +220,15 @@ typedef struct {
 
 /* Launch configuration.  strategy: 1 = attempt-parallel (each lane of a walk
  * evaluates a different random flip attempt; capacity <= 64 only),
- * 2 = term-parallel (the lanes of a walk split its terms; any capacity).
+ * 2 = term-parallel (the lanes of a walk split its terms; any capacity),
+ * 3 = indexed attempt-parallel (strategy 1 over a match index kept in LDS:
+ * per term and factor kind, a mask of the terms with an equal factor;
+ * capacity <= 64 only).
  * lanes_per_walk: 8, 16, 32 or 64 (8, 4, 2 or 1 walks per 64-lane
- * wavefront; at most 32 for attempt-parallel).  waves_per_block: 1..4.
- * A zero field lets the library choose.  Results never depend on it. */
+ * wavefront; at most 32 for the attempt-parallel strategies).
+ * waves_per_block: 1..4.  A zero field lets the library choose (a launch
+ * chosen by tsf_autotune for batches of this shape, else strategy 1 or 2).
+ * Results never depend on it. */
 typedef struct {
     int32_t lanes_per_walk;
     int32_t waves_per_block;
@@ -345,7 +350,7 @@ tsf_status tsf_mlp_bwd(const tsf_mlp *net, const uint16_t *X, const float *y, in
                        uint16_t *d1, float *d3, float *loss, void *hip_stream);
 
 /* Walks with the learned proposal.  Each iteration: the first K = flip_tries
- * random attempts (K <= lanes_per_walk - 1, attempt-parallel strategy) each
+ * random attempts (K <= lanes_per_walk - 1, attempt-parallel strategy 1) each
  * yield their candidate flip exactly as with uniform proposals; the network
  * scores the K candidates (rows of the same feature layout as
  * tsf_features_from_log) and the walk applies the highest-scored one (ties:

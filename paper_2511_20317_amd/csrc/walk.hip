@@ -8,10 +8,10 @@
 #include <vector>
 
 namespace tsfk {
-KernelFn pick_kernel_w0_z0(int g, int s, bool ap);
-KernelFn pick_kernel_w0_z1(int g, int s, bool ap);
-KernelFn pick_kernel_w1_z0(int g, int s, bool ap);
-KernelFn pick_kernel_w1_z1(int g, int s, bool ap);
+KernelFn pick_kernel_w0_z0(int g, int s, int strategy);
+KernelFn pick_kernel_w0_z1(int g, int s, int strategy);
+KernelFn pick_kernel_w1_z0(int g, int s, int strategy);
+KernelFn pick_kernel_w1_z1(int g, int s, int strategy);
 }  // namespace tsfk
 
 namespace {
@@ -248,10 +248,10 @@ __global__ void __launch_bounds__(256) features_kernel(const tsf_flip_log *log, 
 // ---------------------------------------------------------------------------
 // host side: kernel table and launch
 // ---------------------------------------------------------------------------
-KernelFn pick_kernel(int g, int s, bool wide, bool z2, bool ap)
+KernelFn pick_kernel(int g, int s, bool wide, bool z2, int strategy)
 {
-    if (wide) return z2 ? pick_kernel_w1_z1(g, s, ap) : pick_kernel_w1_z0(g, s, ap);
-    return z2 ? pick_kernel_w0_z1(g, s, ap) : pick_kernel_w0_z0(g, s, ap);
+    if (wide) return z2 ? pick_kernel_w1_z1(g, s, strategy) : pick_kernel_w1_z0(g, s, strategy);
+    return z2 ? pick_kernel_w0_z1(g, s, strategy) : pick_kernel_w0_z0(g, s, strategy);
 }
 
 int slots_for(int cap, int g)
@@ -394,7 +394,7 @@ struct Launch {
     dim3 grid, block;
     size_t lds;
     int g;
-    bool ap;
+    bool ap, ix;
 };
 
 // validate a walk call and build its kernel arguments and launch shape
@@ -411,11 +411,12 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (n_iters < 0) return tsf_fail(TSF_E_ARG, "n_iters < 0");
     if (b->log && b->log_cap < 0) return tsf_fail(TSF_E_ARG, "log_cap < 0");
     int strategy = launch ? launch->strategy : 0;
-    if (strategy < 0 || strategy > 2) return tsf_fail(TSF_E_ARG, "strategy %d not in 0..2", strategy);
+    if (strategy < 0 || strategy > 3) return tsf_fail(TSF_E_ARG, "strategy %d not in 0..3", strategy);
     if (strategy == 0) strategy = b->capacity <= 64 ? 1 : 2;
-    const bool ap = strategy == 1;
+    const bool ap = strategy == 1 || strategy == 3;
+    const bool ix = strategy == 3;
     if (ap && b->capacity > 64)
-        return tsf_fail(TSF_E_CAPACITY, "the attempt-parallel strategy needs capacity <= 64");
+        return tsf_fail(TSF_E_CAPACITY, "the attempt-parallel strategies need capacity <= 64");
     int g = launch && launch->lanes_per_walk ? launch->lanes_per_walk : (ap ? 8 : 64);
     int wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4;
     if (g != 8 && g != 16 && g != 32 && g != 64)
@@ -428,12 +429,14 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
         return tsf_fail(TSF_E_CAPACITY, "capacity %d needs more than 8 slots at %d lanes/walk",
                         b->capacity, g);
     const bool wide = b->max_len > 32;
-    L.fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, ap);
+    L.fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, strategy);
     if (!L.fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
     const size_t word = wide ? 8 : 4;
     const int walks_per_wave = 64 / g;
     const int cap2 = b->capacity + (b->capacity & 1);
-    L.lds = (size_t)wpb * walks_per_wave * cap2 * 6 * word;
+    // per walk: the terms, and for the indexed strategy 3 match masks per term
+    const size_t per_walk = (size_t)cap2 * 6 * word + (ix ? (size_t)cap2 * 3 * 8 : 0);
+    L.lds = (size_t)wpb * walks_per_wave * per_walk;
     if (L.lds > 160 * 1024)
         return tsf_fail(TSF_E_CAPACITY, "%zu bytes of LDS per workgroup exceed 160 KiB", L.lds);
     std::memset(&a, 0, sizeof a);
@@ -466,6 +469,7 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     L.block = dim3(64 * wpb);
     L.g = g;
     L.ap = ap;
+    L.ix = ix;
     if (L.lds > 64 * 1024 &&
         hipFuncSetAttribute((const void *)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)L.lds) != hipSuccess)
@@ -544,7 +548,8 @@ tsf_status tsf_autotune(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk
     std::vector<tsf_launch> cands;
     for (int wpb : {1, 2, 4}) {
         if (b->capacity <= 64)
-            for (int g : {8, 16}) cands.push_back(tsf_launch{g, wpb, 1});
+            for (int st : {3, 1})
+                for (int g : {8, 16}) cands.push_back(tsf_launch{g, wpb, st});
         for (int g : {16, 32, 64}) cands.push_back(tsf_launch{g, wpb, 2});
     }
     hipEvent_t e0, e1;
@@ -592,10 +597,16 @@ tsf_status tsf_walk_learned(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_
                             const tsf_mlp *net, const tsf_learn_ws *ws, int64_t n_iters,
                             const tsf_launch *launch, void *hip_stream)
 {
-    (void)ctx;
     KArgs a;
     Launch L;
-    tsf_status st = prepare_walk(prm, b, n_iters, launch, a, L);
+    // the propose and apply phases are kernels of the plain attempt-parallel
+    // strategy (the scheme is reloaded by every launch, so an index would be
+    // rebuilt each time)
+    tsf_launch la = launch ? *launch : tsf_launch{0, 0, 0};
+    if (la.strategy == 0) la.strategy = 1;
+    if (la.strategy != 1)
+        return tsf_fail(TSF_E_ARG, "learned proposals use the attempt-parallel strategy 1");
+    tsf_status st = prepare_walk(prm, b, n_iters, &la, a, L);
     if (st) return st;
     if (!L.ap)
         return tsf_fail(TSF_E_CAPACITY,

@@ -16,36 +16,45 @@ namespace tsfk {
 using Word = std::conditional_t<TSFK_WIDE != 0, uint64_t, uint32_t>;
 constexpr bool kZ2 = TSFK_Z2 != 0;
 
-template <int G, bool AP>
+// term-parallel kernels: S = term slots per lane
+template <int G>
 KernelFn pick_s(int s)
 {
     switch (s) {
-    case 1: return walk_kernel<G, 1, Word, kZ2, AP>;
-    case 2: return walk_kernel<G, 2, Word, kZ2, AP>;
-    case 4: return walk_kernel<G, 4, Word, kZ2, AP>;
-    case 8: return walk_kernel<G, 8, Word, kZ2, AP>;
+    case 1: return walk_kernel<G, 1, Word, kZ2, false, false>;
+    case 2: return walk_kernel<G, 2, Word, kZ2, false, false>;
+    case 4: return walk_kernel<G, 4, Word, kZ2, false, false>;
+    case 8: return walk_kernel<G, 8, Word, kZ2, false, false>;
     default: return nullptr;
     }
 }
 
+// attempt-parallel kernels (schemes of at most 64 terms), plain or indexed
+template <int G>
+KernelFn pick_ap(bool ix)
+{
+    return ix ? walk_kernel<G, 1, Word, kZ2, true, true> : walk_kernel<G, 1, Word, kZ2, true, false>;
+}
+
 #define TSF_CAT2(a, b, c) pick_kernel_w##a##_z##b##c
 #define TSF_CAT(a, b) TSF_CAT2(a, b, )
-// ap: attempt-parallel (schemes of at most 64 terms) or term-parallel
-KernelFn TSF_CAT(TSFK_WIDE, TSFK_Z2)(int g, int s, bool ap)
+// strategy: 1 attempt-parallel, 2 term-parallel, 3 indexed attempt-parallel
+KernelFn TSF_CAT(TSFK_WIDE, TSFK_Z2)(int g, int s, int strategy)
 {
-    if (ap) {
+    if (strategy == 1 || strategy == 3) {
+        const bool ix = strategy == 3;
         switch (g) {
-        case 8: return pick_s<8, true>(s);
-        case 16: return pick_s<16, true>(s);
-        case 32: return pick_s<32, true>(s);
+        case 8: return pick_ap<8>(ix);
+        case 16: return pick_ap<16>(ix);
+        case 32: return pick_ap<32>(ix);
         default: return nullptr;
         }
     }
     switch (g) {
-    case 8: return pick_s<8, false>(s);
-    case 16: return pick_s<16, false>(s);
-    case 32: return pick_s<32, false>(s);
-    case 64: return pick_s<64, false>(s);
+    case 8: return pick_s<8>(s);
+    case 16: return pick_s<16>(s);
+    case 32: return pick_s<32>(s);
+    case 64: return pick_s<64>(s);
     default: return nullptr;
     }
 }

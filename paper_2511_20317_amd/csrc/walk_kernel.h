@@ -29,7 +29,14 @@
 //    the two roles for the few matches only;
 //  * term-parallel (TP, any size): attempts run one after another and the G
 //    lanes split the terms (slot q of lane l is term q*G + l), with one group
-//    ballot per slot and role.
+//    ballot per slot and role;
+//  * indexed attempt-parallel (IX, at most 64 terms): AP over a match index
+//    kept in LDS next to the terms -- for every term k and factor kind X a
+//    64-bit mask of the other live terms whose factor X equals that of k (w
+//    up to sign).  A flip changes two factors, so the index is refreshed in
+//    two lane-parallel passes over the terms, and both the partner scan of
+//    an attempt and the two-shared-factors search of a reduction become mask
+//    lookups.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -136,13 +143,15 @@ __device__ __forceinline__ int kth_bit(uint64_t m, int c)
     return __builtin_ctzll(m);
 }
 
-template <int G, int S, typename T, bool Z2, bool AP>
+template <int G, int S, typename T, bool Z2, bool AP, bool IX>
 struct Walker {
+    static_assert(!IX || AP, "the match index extends the attempt-parallel strategy");
     // group geometry
     int gl;      // lane within the group
     int gshift;  // first lane of the group within the wavefront
     int cap2;
     T *lds;
+    uint64_t *mk;  // IX: match masks, mk[X*cap2 + k]
     // walk scalars, identical in every lane of the group
     uint64_t seed;
     int r, r_cap, best_rank, start_rank, target, n_rec;
@@ -163,6 +172,7 @@ struct Walker {
 
     __device__ __forceinline__ void update_scan_end()
     {
+        if constexpr (IX) return;
         int m = 0;
 #pragma unroll
         for (int g = 0; g < 64 / G; ++g) m = max(m, __builtin_amdgcn_readlane(r, g * G));
@@ -218,6 +228,79 @@ struct Walker {
         return 0;
     }
 
+    // factor X of two terms equal (w also when negated, ternary only): the
+    // relation of the match index
+    __device__ __forceinline__ static bool equiv(TV<T> x, TV<T> y, int X)
+    {
+        if (x.d != y.d) return false;
+        if constexpr (Z2) return true;
+        return x.s == y.s || (X == 2 && (x.s ^ x.d) == y.s);
+    }
+
+    // largest rank of the walks of this wavefront (a wave-uniform loop bound)
+    __device__ __forceinline__ int wave_max_r() const
+    {
+        int m = 0;
+#pragma unroll
+        for (int g = 0; g < 64 / G; ++g) m = max(m, __builtin_amdgcn_readlane(r, g * G));
+        return min(m, a->cap);  // lanes of groups that left early hold no rank
+    }
+
+    // ------------------------------------------------------------ index (IX)
+    // mk[X*cap2 + k], k < r: bit j set iff j != k, j < r and equiv(factor X
+    // of j, factor X of k).  Built from scratch after a scheme is loaded.
+    __device__ void build_index()
+    {
+        for (int k = gl; k < r; k += G) {
+#pragma unroll
+            for (int X = 0; X < 3; ++X) {
+                const TV<T> xk = ld(k, X);
+                uint64_t m = 0;
+                for (int j = 0; j < r; ++j)
+                    m |= (j != k && equiv(ld(j, X), xk, X)) ? (1ull << j) : 0ull;
+                mk[X * cap2 + k] = m;
+            }
+        }
+        wave_lds_sync();
+    }
+
+    // Factor X1 of term k1 (and factor X2 != X1 of term k2 when k2 >= 0) has
+    // been rewritten in LDS: recompute its mask and toggle bit k1 in the
+    // masks of the terms whose relation to it changed.  fresh1: k1 is a new
+    // slot whose old mask is empty.  Lane l handles the terms l, l+G, ...
+    __device__ void refresh(int k1, int X1, int k2, int X2, bool fresh1)
+    {
+        const bool two = k2 >= 0;
+        const TV<T> n1 = ld(k1, X1);
+        const uint64_t o1 = fresh1 ? 0ull : mk[X1 * cap2 + k1];
+        TV<T> n2 = n1;
+        uint64_t o2 = 0;
+        if (two) {
+            n2 = ld(k2, X2);
+            o2 = mk[X2 * cap2 + k2];
+        }
+        uint64_t m1 = 0, m2 = 0;
+        for (int q = 0; q * G < r; ++q) {
+            const int j = q * G + gl;
+            bool e1 = false, e2 = false;
+            if (j < r) {
+                e1 = j != k1 && equiv(ld(j, X1), n1, X1);
+                if (e1 != (((o1 >> j) & 1ull) != 0)) mk[X1 * cap2 + j] ^= 1ull << k1;
+                if (two) {
+                    e2 = j != k2 && equiv(ld(j, X2), n2, X2);
+                    if (e2 != (((o2 >> j) & 1ull) != 0)) mk[X2 * cap2 + j] ^= 1ull << k2;
+                }
+            }
+            m1 |= gballot(e1) << (q * G);
+            m2 |= gballot(e2) << (q * G);
+        }
+        if (gl == 0) {
+            mk[X1 * cap2 + k1] = m1;
+            if (two) mk[X2 * cap2 + k2] = m2;
+        }
+        wave_lds_sync();
+    }
+
     // Sec. 3.6 on a term held in registers: first non-zero of u, then of v,
     // made positive; w absorbs.
     __device__ __forceinline__ static void normalise_regs(TV<T> (&f)[3])
@@ -255,6 +338,23 @@ struct Walker {
         const int last = r - 1;
         if (tr0 == h) tr0 = -1;
         if (tr1 == h) tr1 = -1;
+        if constexpr (IX) {
+            // drop bit h from every mask; bit `last` becomes bit h, and the
+            // masks of term `last` move to slot h
+            const uint64_t bh = 1ull << h, bl = 1ull << last;
+            for (int q = 0; q * G < r; ++q) {
+                const int j = q * G + gl;
+                if (j < r && j != h) {
+                    const int dst = j == last ? h : j;
+#pragma unroll
+                    for (int X = 0; X < 3; ++X) {
+                        uint64_t m = mk[X * cap2 + j] & ~bh;
+                        if (m & bl) m = (m & ~bl) | bh;
+                        mk[X * cap2 + dst] = m;
+                    }
+                }
+            }
+        }
         if (h != last) {
             if (gl < 6) {
                 const int X = gl >> 1, w = gl & 1;
@@ -347,6 +447,7 @@ struct Walker {
         st(i, Y, ny);
         st(j, Z, nz);
         wave_lds_sync();
+        if constexpr (IX) refresh(i, Y, j, Z, false);
     }
 
     // random words of flip attempt `att`: from the lane that drew them in this
@@ -423,6 +524,10 @@ struct Walker {
     __device__ void candidates_ap(int i, int X, uint64_t &m0, uint64_t &m1) const
     {
         const TV<T> xi = ld(i, X);
+        uint64_t match;
+        if constexpr (IX) {
+            match = mk[X * cap2 + i];
+        } else {
         const T nsi = (!Z2 && X == 2) ? (xi.s ^ xi.d) : xi.s;  // accepted signs besides xi.s
         const T *col = lds + idx(0, X);
         const int kend = scan_end;  // even, wave-uniform
@@ -440,8 +545,9 @@ struct Walker {
             hi |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
             hi |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
         }
-        uint64_t match = ((uint64_t)hi << 32) | lo;
+        match = ((uint64_t)hi << 32) | lo;
         match &= (r >= 64 ? ~0ull : ((1ull << r) - 1)) & ~(1ull << i);
+        }
         m0 = m1 = 0;
         if (match == 0) return;
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
@@ -636,7 +742,12 @@ struct Walker {
                                 int &ka, int &kb) const
     {
         ka = kb = -1;
-        const int qend = (a->cap + G - 1) / G;
+        if constexpr (IX) {
+            ka = ia >= 0 ? first_merge(ia, ta) : -1;
+            kb = ib >= 0 ? first_merge(ib, tb) : -1;
+            return;
+        }
+        const int qend = (wave_max_r() + G - 1) / G;
 #pragma unroll 1
         for (int q = 0; q < qend; ++q) {
             const int kk = q * G + gl;
@@ -654,6 +765,21 @@ struct Walker {
             if (ka < 0 && ma) ka = q * G + __builtin_ctzll(ma);
             if (kb < 0 && mb) kb = q * G + __builtin_ctzll(mb);
         }
+    }
+
+    // IX: the terms sharing two factors with term ti are the pairwise
+    // intersections of its three masks; the first (ascending) whose merge
+    // keeps the coefficients in the set, or -1
+    __device__ int first_merge(int ti, const TV<T> (&tt)[3]) const
+    {
+        const uint64_t mu = mk[ti], mv = mk[cap2 + ti], mw = mk[2 * cap2 + ti];
+        for (uint64_t c = (mu & mv) | (mu & mw) | (mv & mw); c; c &= c - 1) {
+            const int k = __builtin_ctzll(c);
+            TV<T> tk[3], o;
+            load_term(k, tk);
+            if (merge_kind(tt, tk, o) >= 0) return k;
+        }
+        return -1;
     }
 
     // merge term k into tracked term qq (Sec. 3.3.1 reduction); the merged
@@ -684,6 +810,12 @@ struct Walker {
         normalise_regs(nt);
         store_term(lo, nt);
         wave_lds_sync();
+        if constexpr (IX) {
+            // the merged factor is new at slot lo; the two shared factors are
+            // those of the term that held lo (w possibly negated, which the
+            // index ignores)
+            refresh(lo, kind, -1, 0, false);
+        }
         if (qq == 0)
             tr0 = lo;
         else
@@ -766,6 +898,16 @@ struct Walker {
             normalise(i);
             normalise(j);
             normalise(nw);
+            if constexpr (IX) {
+                // one factor at a time: each refresh starts from masks that
+                // are exact for every factor already refreshed
+#pragma unroll 1
+                for (int x = 0; x < 3; ++x) refresh(nw, x, -1, 0, true);
+#pragma unroll 1
+                for (int x = 0; x < 3; ++x) refresh(i, x, -1, 0, false);
+#pragma unroll 1
+                for (int x = 0; x < 3; ++x) refresh(j, x, -1, 0, false);
+            }
             cnt[C_EXPANDS]++;
             return true;
         }
@@ -782,6 +924,12 @@ struct Walker {
 #pragma unroll
             for (int x = 0; x < 6; ++x) lds[idx(k, x >> 1) + (x & 1)] = (T)src[k * 6 + x];
         wave_lds_sync();
+        if constexpr (IX) {
+            const int keep = r;
+            r = rr;
+            build_index();
+            r = keep;
+        }
     }
     __device__ void store_scheme(uint64_t *dst) const
     {
@@ -975,7 +1123,7 @@ __device__ __forceinline__ int flen(int m, int n, int p, int X)
     return X == 0 ? m * n : X == 1 ? n * p : p * m;
 }
 
-template <int G, int S, typename T, bool Z2, bool AP>
+template <int G, int S, typename T, bool Z2, bool AP, bool IX>
 __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
 {
     extern __shared__ uint64_t smem_u64[];
@@ -987,11 +1135,14 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
     const int64_t walk = ((int64_t)blockIdx.x * wpb + wave) * W + grp;
     if (walk >= a.n_walks) return;  // the whole group leaves together
 
-    Walker<G, S, T, Z2, AP> wk;
+    Walker<G, S, T, Z2, AP, IX> wk;
     wk.gl = lane % G;
     wk.gshift = grp * G;
     wk.cap2 = a.cap2;
-    wk.lds = smem + (size_t)(wave * W + grp) * a.cap2 * 6;
+    // per walk: the terms (6*cap2 words), then for IX the masks (3*cap2 u64)
+    const size_t stride = (size_t)a.cap2 * 6 + (IX ? (size_t)a.cap2 * 3 * (8 / sizeof(T)) : 0);
+    wk.lds = smem + (size_t)(wave * W + grp) * stride;
+    wk.mk = reinterpret_cast<uint64_t *>(wk.lds + (size_t)a.cap2 * 6);
     wk.a = &a;
     wk.walk = walk;
     tsf_walk_header *h = a.hdr + walk;
@@ -1023,7 +1174,7 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
     wk.fmt_slot = format_slot(m, n, p);
     wk.load_scheme(a.cur + (size_t)walk * a.cap * 6, wk.r);
 
-    if constexpr (AP) {
+    if constexpr (AP && !IX) {
         if (a.phase == 1) {
             // learned proposal, phase 1: candidates and feature rows only
             if (wk.best_rank <= wk.target || wk.t >= a.max_iters) return;
@@ -1032,11 +1183,11 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
             return;
         }
     }
-    if (AP && a.phase == 2) {
+    if (AP && !IX && a.phase == 2) {
         if (wk.best_rank <= wk.target) done = 1;
         if (!done && wk.t < a.max_iters) {
             wk.t += 1;
-            if constexpr (AP) wk.apply_learned();
+            if constexpr (AP && !IX) wk.apply_learned();
         }
     } else {
         for (int64_t it = 0; it < a.n_iters; ++it) {

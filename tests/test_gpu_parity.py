@@ -49,9 +49,10 @@ def test_config1_2x2x2_all_walks(ctx):
 
 
 @pytest.mark.parametrize("lanes,wpb,strategy", [(8, 4, 1), (16, 2, 1), (32, 1, 1), (8, 4, 2),
-                                                (16, 2, 2), (32, 1, 2), (64, 4, 2)])
+                                                (16, 2, 2), (32, 1, 2), (64, 4, 2), (8, 4, 3),
+                                                (16, 2, 3), (32, 1, 3), (8, 1, 3)])
 def test_launch_shape_and_round_split_invariance(ctx, lanes, wpb, strategy):
-    """Both flip-search strategies, every lanes-per-walk choice, rounds split
+    """Every flip-search strategy, every lanes-per-walk choice, rounds split
     unevenly: identical to the oracle."""
     groups = [(_std(3, 3, 3), 48, 35, 23)]
     prm = tsf.walk_params(base_seed=7, max_iters=3000, plateau=1000, t_expand=1 << 28)
@@ -66,21 +67,37 @@ def test_flip_tries_across_batches(ctx, tries):
     groups = [(_std(2, 2, 3), 32, 20, 0), (_std(3, 3, 3), 32, 35, 23)]
     prm = tsf.walk_params(base_seed=21, max_iters=4000, plateau=1500, flip_tries=tries,
                           t_expand=1 << 28)
-    for strategy in (1, 2):
-        b = _run(ctx, groups, prm, 4000, strategy=strategy, lanes=8 if strategy == 1 else 16)
+    for strategy in (1, 2, 3):
+        b = _run(ctx, groups, prm, 4000, strategy=strategy, lanes=16 if strategy == 2 else 8)
         compare(b, run_oracle(groups, prm, range(64), 4000), "tries=%d s=%d" % (tries, strategy))
 
 
-def test_3x3x3_restarts_expand_partial_reduce(ctx):
+@pytest.mark.parametrize("strategy", [1, 3])
+def test_3x3x3_restarts_expand_partial_reduce(ctx, strategy):
     groups = [(_std(3, 3, 3), 32, 35, 23)]
     prm = tsf.walk_params(base_seed=11, max_iters=20000, plateau=3000, t_expand=1 << 28,
                           t_reduce=1 << 31, restart_from_best=0)
-    b = _run(ctx, groups, prm, 20000)
-    compare(b, run_oracle(groups, prm, range(32), 20000), "333 mix")
+    b = _run(ctx, groups, prm, 20000, strategy=strategy)
+    compare(b, run_oracle(groups, prm, range(32), 20000), "333 mix s=%d" % strategy)
     prm2 = tsf.walk_params(base_seed=12, max_iters=8000, plateau=2000, restart_from_best=1,
                            t_expand=1 << 27)
-    b = _run(ctx, groups, prm2, 8000, splits=[3000, 5000])
-    compare(b, run_oracle(groups, prm2, range(32), 8000), "333 restart-best")
+    b = _run(ctx, groups, prm2, 8000, splits=[3000, 5000], strategy=strategy)
+    compare(b, run_oracle(groups, prm2, range(32), 8000), "333 restart-best s=%d" % strategy)
+
+
+@pytest.mark.parametrize("lanes", [8, 16, 32])
+def test_indexed_strategy_small_mixed_formats_heavy_expand(ctx, lanes):
+    """The match index under every kind of update: frequent expands (plus and
+    split append terms), merges and zero-term removals, restarts, and walks of
+    different formats and ranks sharing a wavefront."""
+    fmts = [(2, 2, 2), (2, 2, 3), (2, 3, 3), (3, 3, 3)]
+    groups = [(_std(*f), 12, min(f[0] * f[1] * f[2] + 16, 64), 0) for f in fmts]
+    prm = tsf.walk_params(base_seed=41, max_iters=5000, plateau=1500, t_expand=1 << 30,
+                          t_reduce=3 << 30)
+    b = _run(ctx, groups, prm, 5000, splits=[2500, 2500], lanes=lanes, strategy=3)
+    compare(b, run_oracle(groups, prm, range(48), 5000), "ix mixed G=%d" % lanes)
+    cnt = b.headers()["counters"]
+    assert cnt[:, 7].sum() > 0 and cnt[:, 6].sum() > 0  # expands and merges happened
 
 
 def test_mixed_formats_one_launch(ctx):
@@ -92,7 +109,7 @@ def test_mixed_formats_one_launch(ctx):
         compare(b, run_oracle(groups, prm, range(48), 2000), "mixed G=%d" % lanes)
 
 
-@pytest.mark.parametrize("strategy", [1, 2])
+@pytest.mark.parametrize("strategy", [1, 2, 3])
 def test_z2_mode(ctx, strategy):
     groups = [(_std(2, 2, 2, tsf.TSF_Z2), 32, 16, 7), (_std(3, 3, 4, tsf.TSF_Z2), 16, 44, 0)]
     prm = tsf.walk_params(base_seed=5, max_iters=6000, plateau=2000, t_expand=1 << 27)
