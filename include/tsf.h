@@ -224,10 +224,12 @@ typedef struct {
  * 3 = indexed attempt-parallel (strategy 1 over a match index kept in LDS:
  * per term and factor kind, a mask of the terms with an equal factor;
  * capacity <= 64 only).
- * lanes_per_walk: 8, 16, 32 or 64 (8, 4, 2 or 1 walks per 64-lane
- * wavefront; at most 32 for the attempt-parallel strategies).
- * waves_per_block: 1..4.  A zero field lets the library choose (a launch
- * chosen by tsf_autotune for batches of this shape, else strategy 1 or 2).
+ * lanes_per_walk: 4, 8, 16, 32 or 64 (16, 8, 4, 2 or 1 walks per 64-lane
+ * wavefront; 4 to 32 for the attempt-parallel strategies, 8 to 64 for the
+ * term-parallel one).  waves_per_block: 1..4.  A zero field lets the library
+ * choose (a launch chosen by tsf_autotune for batches of this shape, else
+ * strategy 3 with 8 lanes and 1 wavefront per workgroup up to capacity 64,
+ * strategy 2 with 64 lanes and 4 wavefronts beyond).
  * Results never depend on it. */
 typedef struct {
     int32_t lanes_per_walk;

@@ -412,19 +412,22 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (b->log && b->log_cap < 0) return tsf_fail(TSF_E_ARG, "log_cap < 0");
     int strategy = launch ? launch->strategy : 0;
     if (strategy < 0 || strategy > 3) return tsf_fail(TSF_E_ARG, "strategy %d not in 0..3", strategy);
-    if (strategy == 0) strategy = b->capacity <= 64 ? 1 : 2;
+    if (strategy == 0) strategy = b->capacity <= 64 ? 3 : 2;
     const bool ap = strategy == 1 || strategy == 3;
     const bool ix = strategy == 3;
     if (ap && b->capacity > 64)
         return tsf_fail(TSF_E_CAPACITY, "the attempt-parallel strategies need capacity <= 64");
     int g = launch && launch->lanes_per_walk ? launch->lanes_per_walk : (ap ? 8 : 64);
-    int wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4;
-    if (g != 8 && g != 16 && g != 32 && g != 64)
-        return tsf_fail(TSF_E_ARG, "lanes_per_walk %d not in {8,16,32,64}", g);
+    int wpb = launch && launch->waves_per_block ? launch->waves_per_block : (ap ? 1 : 4);
+    if (g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
+        return tsf_fail(TSF_E_ARG, "lanes_per_walk %d not in {4,8,16,32,64}", g);
+    if (g == 4 && !ap)
+        return tsf_fail(TSF_E_ARG, "4 lanes per walk only with the attempt-parallel strategies");
     if (ap && g == 64)
-        return tsf_fail(TSF_E_ARG, "the attempt-parallel strategy uses 8, 16 or 32 lanes per walk");
+        return tsf_fail(TSF_E_ARG, "the attempt-parallel strategies use 4 to 32 lanes per walk");
     if (wpb < 1 || wpb > 4) return tsf_fail(TSF_E_ARG, "waves_per_block %d not in 1..4", wpb);
-    const int s = slots_for(b->capacity, g);
+    // term slots per lane (the term-parallel kernels only)
+    const int s = ap ? 1 : slots_for(b->capacity, g);
     if (s < 0)
         return tsf_fail(TSF_E_CAPACITY, "capacity %d needs more than 8 slots at %d lanes/walk",
                         b->capacity, g);
@@ -433,7 +436,9 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (!L.fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
     const size_t word = wide ? 8 : 4;
     const int walks_per_wave = 64 / g;
-    const int cap2 = b->capacity + (b->capacity & 1);
+    // LDS stride per factor kind: capacity rounded up to even (to a multiple
+    // of 4 for the indexed strategy, which reads four terms at a time)
+    const int cap2 = ix ? (b->capacity + 3) & ~3 : b->capacity + (b->capacity & 1);
     // per walk: the terms, and for the indexed strategy 3 match masks per term
     const size_t per_walk = (size_t)cap2 * 6 * word + (ix ? (size_t)cap2 * 3 * 8 : 0);
     L.lds = (size_t)wpb * walks_per_wave * per_walk;
@@ -549,7 +554,7 @@ tsf_status tsf_autotune(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk
     for (int wpb : {1, 2, 4}) {
         if (b->capacity <= 64)
             for (int st : {3, 1})
-                for (int g : {8, 16}) cands.push_back(tsf_launch{g, wpb, st});
+                for (int g : {4, 8, 16}) cands.push_back(tsf_launch{g, wpb, st});
         for (int g : {16, 32, 64}) cands.push_back(tsf_launch{g, wpb, 2});
     }
     hipEvent_t e0, e1;

@@ -44,6 +44,7 @@ KernelFn TSF_CAT(TSFK_WIDE, TSFK_Z2)(int g, int s, int strategy)
     if (strategy == 1 || strategy == 3) {
         const bool ix = strategy == 3;
         switch (g) {
+        case 4: return pick_ap<4>(ix);
         case 8: return pick_ap<8>(ix);
         case 16: return pick_ap<16>(ix);
         case 32: return pick_ap<32>(ix);

@@ -59,7 +59,7 @@ struct KArgs {
     int32_t rec_cap;
     int32_t mode;
     int32_t max_len;
-    int32_t cap2;  // LDS stride per factor kind: cap rounded up to even
+    int32_t cap2;  // LDS stride per factor kind: cap rounded up to even (IX: to 4)
     tsf_walk_header *hdr;
     uint64_t *cur;
     uint64_t *best;
@@ -135,6 +135,13 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 __device__ __forceinline__ int popc64(uint64_t x) { return __builtin_popcountll(x); }
+
+// x ^= v on a 64-bit LDS word, as an atomic that returns nothing
+__device__ __forceinline__ void lds_xor(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_fetch_xor((__attribute__((address_space(3))) uint64_t *)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
 
 // index of the c-th (0-based) set bit of m (m has more than c bits set)
 __device__ __forceinline__ int kth_bit(uint64_t m, int c)
@@ -264,39 +271,88 @@ struct Walker {
         wave_lds_sync();
     }
 
-    // Factor X1 of term k1 (and factor X2 != X1 of term k2 when k2 >= 0) has
-    // been rewritten in LDS: recompute its mask and toggle bit k1 in the
-    // masks of the terms whose relation to it changed.  fresh1: k1 is a new
-    // slot whose old mask is empty.  Lane l handles the terms l, l+G, ...
-    __device__ void refresh(int k1, int X1, int k2, int X2, bool fresh1)
+    // factor X of the four consecutive terms jb..jb+3 (jb a multiple of 4;
+    // the IX layout pads cap2 to a multiple of 4) with 16-byte LDS reads
+    __device__ __forceinline__ void load4(int jb, int X, TV<T> (&f)[4]) const
     {
-        const bool two = k2 >= 0;
-        const TV<T> n1 = ld(k1, X1);
-        const uint64_t o1 = fresh1 ? 0ull : mk[X1 * cap2 + k1];
-        TV<T> n2 = n1;
-        uint64_t o2 = 0;
-        if (two) {
-            n2 = ld(k2, X2);
-            o2 = mk[X2 * cap2 + k2];
+        const T *q = lds + idx(jb, X);
+        if constexpr (sizeof(T) == 4) {
+            const uint4 a = *reinterpret_cast<const uint4 *>(q);
+            const uint4 b = *reinterpret_cast<const uint4 *>(q + 4);
+            f[0] = TV<T>{a.x, a.y};
+            f[1] = TV<T>{a.z, a.w};
+            f[2] = TV<T>{b.x, b.y};
+            f[3] = TV<T>{b.z, b.w};
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(q + 2 * e);
+                f[e] = TV<T>{(T)v.x, (T)v.y};
+            }
         }
-        uint64_t m1 = 0, m2 = 0;
-        for (int q = 0; q * G < r; ++q) {
-            const int j = q * G + gl;
-            bool e1 = false, e2 = false;
-            if (j < r) {
-                e1 = j != k1 && equiv(ld(j, X1), n1, X1);
-                if (e1 != (((o1 >> j) & 1ull) != 0)) mk[X1 * cap2 + j] ^= 1ull << k1;
-                if (two) {
-                    e2 = j != k2 && equiv(ld(j, X2), n2, X2);
-                    if (e2 != (((o2 >> j) & 1ull) != 0)) mk[X2 * cap2 + j] ^= 1ull << k2;
+    }
+
+    // Factor X1 of term k1 and factor X2 != X1 of term k2 have been given the
+    // new values n1 and n2 (the two factors a flip changes; o1 and o2 are
+    // their masks before the change).  For every live term j whose
+    // relation to one of them changed, bit k of j's mask and bit j of k's mask
+    // are toggled (LDS atomics, so no lane waits for a read-modify-write).
+    // Lane l handles the four consecutive terms 4l .. 4l+3 of each block of
+    // 4G terms.
+    __device__ void refresh(int k1, int X1, TV<T> n1, uint64_t o1, int k2, int X2, TV<T> n2,
+                            uint64_t o2)
+    {
+        const int rend = wave_max_r();
+        for (int j0 = 0; j0 < rend; j0 += 4 * G) {
+            const int jb = j0 + 4 * gl;
+            if (jb < r) {
+                TV<T> f1[4], f2[4];
+                load4(jb, X1, f1);
+                load4(jb, X2, f2);
+                // nibbles of the four terms: relation now, then changed ones
+                uint32_t c1 = 0, c2 = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    c1 |= equiv(f1[e], n1, X1) ? 1u << e : 0u;
+                    c2 |= equiv(f2[e], n2, X2) ? 1u << e : 0u;
+                }
+                const uint32_t live = (r - jb >= 4 ? 0xFu : (1u << (r - jb)) - 1u);
+                const uint32_t self1 = (uint32_t)(k1 - jb) < 4u ? 1u << (k1 - jb) : 0u;
+                const uint32_t self2 = (uint32_t)(k2 - jb) < 4u ? 1u << (k2 - jb) : 0u;
+                c1 = ((c1 & live & ~self1) ^ (uint32_t)(o1 >> jb)) & 0xFu;
+                c2 = ((c2 & live & ~self2) ^ (uint32_t)(o2 >> jb)) & 0xFu;
+                for (; c1; c1 &= c1 - 1) {
+                    const int j = jb + __builtin_ctz(c1);
+                    lds_xor(mk + X1 * cap2 + j, 1ull << k1);
+                    lds_xor(mk + X1 * cap2 + k1, 1ull << j);
+                }
+                for (; c2; c2 &= c2 - 1) {
+                    const int j = jb + __builtin_ctz(c2);
+                    lds_xor(mk + X2 * cap2 + j, 1ull << k2);
+                    lds_xor(mk + X2 * cap2 + k2, 1ull << j);
                 }
             }
-            m1 |= gballot(e1) << (q * G);
-            m2 |= gballot(e2) << (q * G);
         }
-        if (gl == 0) {
-            mk[X1 * cap2 + k1] = m1;
-            if (two) mk[X2 * cap2 + k2] = m2;
+        wave_lds_sync();
+    }
+
+    // refresh() for one factor, one term per lane and round: used on the rare
+    // paths (merges, expands), where code size and registers matter more
+    __device__ void refresh_one(int k, int X, bool fresh)
+    {
+        const TV<T> nk = ld(k, X);
+        const uint64_t o = fresh ? 0ull : mk[X * cap2 + k];
+        if (fresh) {
+            if (gl == 0) mk[X * cap2 + k] = 0;
+            wave_lds_sync();
+        }
+#pragma unroll 1
+        for (int j = gl; j < r; j += G) {
+            const bool e = j != k && equiv(ld(j, X), nk, X);
+            if (e != (((o >> j) & 1ull) != 0)) {
+                lds_xor(mk + X * cap2 + j, 1ull << k);
+                lds_xor(mk + X * cap2 + k, 1ull << j);
+            }
         }
         wave_lds_sync();
     }
@@ -356,8 +412,8 @@ struct Walker {
             }
         }
         if (h != last) {
-            if (gl < 6) {
-                const int X = gl >> 1, w = gl & 1;
+            for (int q = gl; q < 6; q += G) {
+                const int X = q >> 1, w = q & 1;
                 lds[idx(h, X) + w] = lds[idx(last, X) + w];
             }
             if (tr0 == last) tr0 = h;
@@ -444,10 +500,29 @@ struct Walker {
                 st(j, 2, w);
             }
         }
+        if constexpr (IX) {
+            const uint64_t oy = mk[Y * cap2 + i], oz = mk[Z * cap2 + j];
+            st(i, Y, ny);
+            st(j, Z, nz);
+            if (!zi && !zj) {
+                // the refresh compares the new factors (in registers) with
+                // factors of other terms only, which these stores do not
+                // change (w only up to sign), so it needs no barrier first
+                refresh(i, Y, ny, oy, j, Z, nz, oz);
+                return;
+            }
+            wave_lds_sync();
+            // a term with a zero factor is removed next, and its removal
+            // clears its bit from every mask: only a survivor is refreshed
+            if (!zi)
+                refresh_one(i, Y, false);
+            else if (!zj)
+                refresh_one(j, Z, false);
+            return;
+        }
         st(i, Y, ny);
         st(j, Z, nz);
         wave_lds_sync();
-        if constexpr (IX) refresh(i, Y, j, Z, false);
     }
 
     // random words of flip attempt `att`: from the lane that drew them in this
@@ -743,8 +818,10 @@ struct Walker {
     {
         ka = kb = -1;
         if constexpr (IX) {
-            ka = ia >= 0 ? first_merge(ia, ta) : -1;
-            kb = ib >= 0 ? first_merge(ib, tb) : -1;
+            const uint64_t ca = ia >= 0 ? two_shared(ia) : 0ull;
+            const uint64_t cb = ib >= 0 ? two_shared(ib) : 0ull;
+            ka = first_merge(ca, ta);
+            kb = first_merge(cb, tb);
             return;
         }
         const int qend = (wave_max_r() + G - 1) / G;
@@ -768,12 +845,17 @@ struct Walker {
     }
 
     // IX: the terms sharing two factors with term ti are the pairwise
-    // intersections of its three masks; the first (ascending) whose merge
-    // keeps the coefficients in the set, or -1
-    __device__ int first_merge(int ti, const TV<T> (&tt)[3]) const
+    // intersections of its three masks (two_shared); first_merge returns the
+    // first of them (ascending) whose merge keeps the coefficients in the
+    // set, or -1
+    __device__ __forceinline__ uint64_t two_shared(int ti) const
     {
         const uint64_t mu = mk[ti], mv = mk[cap2 + ti], mw = mk[2 * cap2 + ti];
-        for (uint64_t c = (mu & mv) | (mu & mw) | (mv & mw); c; c &= c - 1) {
+        return (mu & mv) | (mu & mw) | (mv & mw);
+    }
+    __device__ int first_merge(uint64_t c, const TV<T> (&tt)[3]) const
+    {
+        for (; c; c &= c - 1) {
             const int k = __builtin_ctzll(c);
             TV<T> tk[3], o;
             load_term(k, tk);
@@ -814,7 +896,7 @@ struct Walker {
             // the merged factor is new at slot lo; the two shared factors are
             // those of the term that held lo (w possibly negated, which the
             // index ignores)
-            refresh(lo, kind, -1, 0, false);
+            refresh_one(lo, kind, false);
         }
         if (qq == 0)
             tr0 = lo;
@@ -902,11 +984,11 @@ struct Walker {
                 // one factor at a time: each refresh starts from masks that
                 // are exact for every factor already refreshed
 #pragma unroll 1
-                for (int x = 0; x < 3; ++x) refresh(nw, x, -1, 0, true);
+                for (int x = 0; x < 3; ++x) refresh_one(nw, x, true);
 #pragma unroll 1
-                for (int x = 0; x < 3; ++x) refresh(i, x, -1, 0, false);
+                for (int x = 0; x < 3; ++x) refresh_one(i, x, false);
 #pragma unroll 1
-                for (int x = 0; x < 3; ++x) refresh(j, x, -1, 0, false);
+                for (int x = 0; x < 3; ++x) refresh_one(j, x, false);
             }
             cnt[C_EXPANDS]++;
             return true;

@@ -50,7 +50,8 @@ def test_config1_2x2x2_all_walks(ctx):
 
 @pytest.mark.parametrize("lanes,wpb,strategy", [(8, 4, 1), (16, 2, 1), (32, 1, 1), (8, 4, 2),
                                                 (16, 2, 2), (32, 1, 2), (64, 4, 2), (8, 4, 3),
-                                                (16, 2, 3), (32, 1, 3), (8, 1, 3)])
+                                                (16, 2, 3), (32, 1, 3), (8, 1, 3), (4, 1, 3),
+                                                (4, 2, 1)])
 def test_launch_shape_and_round_split_invariance(ctx, lanes, wpb, strategy):
     """Every flip-search strategy, every lanes-per-walk choice, rounds split
     unevenly: identical to the oracle."""
@@ -85,7 +86,7 @@ def test_3x3x3_restarts_expand_partial_reduce(ctx, strategy):
     compare(b, run_oracle(groups, prm2, range(32), 8000), "333 restart-best s=%d" % strategy)
 
 
-@pytest.mark.parametrize("lanes", [8, 16, 32])
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
 def test_indexed_strategy_small_mixed_formats_heavy_expand(ctx, lanes):
     """The match index under every kind of update: frequent expands (plus and
     split append terms), merges and zero-term removals, restarts, and walks of
