@@ -25,6 +25,25 @@ sys.path.insert(0, ROOT)
 PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x int32 lanes/clk/CU x clock = 39.3e12 op/s
 PEAK_HBM = 8.0e12
 
+# HBM bytes per walk-kernel launch of the default workload (65,536 walks, 10
+# launches of 1e5 iterations), from two rocprofv3 passes over this script:
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per dispatch, the scales read off a
+# 1 GiB device copy in the same runs (--calibrate-copy-mib 1024), averaged
+# over the ten launches.  Valid only for the kernel sources it was measured
+# on (their SHA-1 below); otherwise the benchmark reports no traffic.
+MEASURED_TRAFFIC = {"sources_sha1": "193649690baac0411d342d776f44e55178311644", "walks": 65536,
+                    "iters": 100000, "steps": 10, "bytes_per_launch": 3448574707}
+KERNEL_SOURCES = ("walk_kernel.h", "walk_inst.hip", "tsf_bits.h")
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2511_20317_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def ops_per_iteration(cnt, iters, mean_rank, wd=1):
     """Algorithmic 32-bit integer operations of one walk iteration, from the
@@ -241,7 +260,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per walk (0: library choice)")
     ap.add_argument("--wpb", type=int, default=0, help="waves per workgroup (0: library choice)")
     ap.add_argument("--strategy", type=int, default=0,
-                    help="1 attempt-parallel, 2 term-parallel (0: library choice)")
+                    help="1 attempt-parallel, 2 term-parallel, 3 indexed attempt-parallel "
+                         "(0: library choice)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-walks", type=int, default=256)
     ap.add_argument("--cpu-iters", type=int, default=100000)
@@ -345,6 +365,23 @@ def main():
     ops_iter = ops_per_iteration(cnt, iters, (mean_rank + 27) / 2)
     avg_ms = float(np.mean(kernel_ms))
     achieved = ops_iter * per_launch_iters / (avg_ms * 1e-3)
+    traffic = None
+    mt = MEASURED_TRAFFIC
+    if (mt["bytes_per_launch"] and mt["sources_sha1"] == kernel_sources_sha1() and
+            (args.walks, args.iters, args.steps) == (mt["walks"], mt["iters"], mt["steps"])):
+        traffic = mt["bytes_per_launch"]
+    # first iteration at which some walk recorded the target rank (records
+    # are (iteration, rank) of every strict improvement), and its wall time at
+    # the measured iteration rate
+    first_hit = None
+    n_rec = np.minimum(hdr["n_rec"], batch.rec_cap)
+    rec = batch.rec.cpu().numpy()
+    for w in np.flatnonzero(hdr["best_rank"] <= target):
+        its = rec[w, :n_rec[w], 0]
+        rks = rec[w, :n_rec[w], 1] & 0xFFFFFFFF
+        hit = its[rks <= target]
+        if hit.size and (first_hit is None or hit.min() < first_hit):
+            first_hit = int(hit.min())
     ranks = np.bincount(hdr["best_rank"], minlength=28)
     out = {
         "metric": "flips/sec on 1 GPU and time-to-rank-23 at (3,3,3), learned vs uniform proposal",
@@ -365,11 +402,14 @@ def main():
                    "target_rank": target, "seeds": "0..%d" % (args.walks - 1),
                    "lanes_per_walk": args.lanes or "library", "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+                     "unit": "Tops/s", "frac": achieved / PEAK_INT32_OPS, "traffic": traffic,
                      "kernel": "walk_kernel", "kernel_avg_ms": avg_ms,
                      "ops_per_iteration": ops_iter},
         "time_to_rank_s": ladder,
         "time_to_rank_23_s": ladder.get(23),
+        "first_rank_23_iteration": first_hit,
+        "time_to_rank_23_at_iteration_rate_s": (first_hit * wall / (iters / args.walks)
+                                                if first_hit is not None else None),
         "walks_at_rank": {str(r): int(ranks[r]) for r in range(20, 28) if ranks[r]},
         "iterations_per_s": iters / wall,
         "attempts_per_iteration": cnt["attempts"] / iters,
