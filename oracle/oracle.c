@@ -159,14 +159,20 @@ long or_brent_violations(const or_scheme *s)
 }
 
 /* Naive additive complexity (Sec. 4.5): non-zero coefficients - 2r - m*p. */
-long or_naive_additions(const or_scheme *s)
+long or_nonzeros(const or_scheme *s)
 {
     long nnz = 0;
     for (int X = 0; X < 3; ++X)
         for (int l = 0; l < s->r; ++l)
             for (int e = 0; e < or_len(s, X); ++e)
                 if (s->f[X][l][e] != 0) ++nnz;
-    return nnz - 2L * s->r - (long)s->m * s->p;
+    return nnz;
+}
+
+/* Naive additive complexity (Sec. 4.5): non-zero coefficients - 2r - mp. */
+long or_naive_additions(const or_scheme *s)
+{
+    return or_nonzeros(s) - 2L * s->r - (long)s->m * s->p;
 }
 
 /* Sign-symmetry normalisation (Sec. 3.6).  Reading, fixed by the worked
@@ -555,15 +561,35 @@ void or_walk_init(or_walk *w, const or_scheme *start)
     w->cur = w->start;
     w->best = w->start;
     w->best_rank = w->start.r;
+    w->best_nnz = (int32_t)or_nonzeros(&w->start);
 }
 
-/* Is (j, sigma, role) a valid flip partner of (i, X)? */
-static int partner(const or_scheme *s, int i, int j, int X, int role, int *sigma)
+/* best := current (the best scheme's non-zero count follows it) */
+static void set_best(or_walk *w)
+{
+    w->best = w->cur;
+    w->best_rank = w->cur.r;
+    w->best_nnz = (int32_t)or_nonzeros(&w->cur);
+}
+
+/* Is (j, sigma, role) a valid flip partner of (i, X)?  keep_rank: also
+ * require that neither modified factor becomes zero (a flip that zeroes a
+ * factor removes a term, which the additions objective excludes). */
+static int partner(const or_scheme *s, int i, int j, int X, int role, int keep_rank, int *sigma)
 {
     if (j == i) return 0;
     int sg = shared_sign(s, i, j, X);
     if (sg == 0) return 0;
     if (!or_flip_valid(s, i, j, X, sg, role)) return 0;
+    if (keep_rank) {
+        int Y, Z;
+        int8_t tmp[OR_MAXL];
+        other_kinds(X, role, &Y, &Z);
+        or_ternary_add(s->f[Y][i], s->f[Y][j], sg, or_len(s, Y), s->z2, tmp);
+        if (vec_zero(tmp, or_len(s, Y))) return 0;
+        or_ternary_add(s->f[Z][j], s->f[Z][i], -1, or_len(s, Z), s->z2, tmp);
+        if (vec_zero(tmp, or_len(s, Z))) return 0;
+    }
     *sigma = sg;
     return 1;
 }
@@ -571,14 +597,14 @@ static int partner(const or_scheme *s, int i, int j, int X, int role, int *sigma
 /* Candidates of the attempt (i, X): the valid (j, role), role 0 then 1, j
  * ascending.  Returns their number; when pick >= 0, the pick-th candidate is
  * written to *pj, *psg, *prole. */
-static int attempt_candidates(const or_scheme *s, int i, int X, long pick, int *pj, int *psg,
-                              int *prole)
+static int attempt_candidates(const or_scheme *s, int i, int X, int keep_rank, long pick, int *pj,
+                              int *psg, int *prole)
 {
     int n = 0;
     for (int role = 0; role < 2; ++role)
         for (int j = 0; j < s->r; ++j) {
             int sg;
-            if (!partner(s, i, j, X, role, &sg)) continue;
+            if (!partner(s, i, j, X, role, keep_rank, &sg)) continue;
             if (n == pick) {
                 *pj = j; *psg = sg; *prole = role;
             }
@@ -606,15 +632,16 @@ static int try_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *p
     int r = s->r;
     uint32_t rw[4];
     int j = -1, sg = 0, role = 0;
+    const int keep = prm->objective == 1;
     if (r < 2) return 0;
     for (int a = 0; a < prm->flip_tries; ++a) {
         draw(prm->seed, t, (uint32_t)a, 0, rw);
         w->c.attempts++;
         int i = uniform_below(rw[0], r);
         int X = uniform_below(rw[1], 3);
-        int n = attempt_candidates(s, i, X, -1, &j, &sg, &role);
+        int n = attempt_candidates(s, i, X, keep, -1, &j, &sg, &role);
         if (n > 0) {
-            attempt_candidates(s, i, X, uniform_below(rw[2], n), &j, &sg, &role);
+            attempt_candidates(s, i, X, keep, uniform_below(rw[2], n), &j, &sg, &role);
             *pi = i; *pj = j; *pX = X; *prole = role;
             return 1;
         }
@@ -630,6 +657,7 @@ static int fallback_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, i
     int r = s->r;
     uint32_t rw[4];
     int j = -1, sg = 0, role = 0;
+    const int keep = prm->objective == 1;
     w->c.fallbacks++;
     draw(prm->seed, t, (uint32_t)prm->flip_tries, 0, rw);
     int npairs = 3 * r;
@@ -637,9 +665,9 @@ static int fallback_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, i
     for (int q = 0; q < npairs; ++q) {
         int p = (p0 + q) % npairs;
         int i = p / 3, X = p % 3;
-        int n = attempt_candidates(s, i, X, -1, &j, &sg, &role);
+        int n = attempt_candidates(s, i, X, keep, -1, &j, &sg, &role);
         if (n == 0) continue;
-        attempt_candidates(s, i, X, uniform_below(rw[1], n), &j, &sg, &role);
+        attempt_candidates(s, i, X, keep, uniform_below(rw[1], n), &j, &sg, &role);
         *pi = i; *pj = j; *pX = X; *prole = role;
         return 1;
     }
@@ -699,6 +727,50 @@ static void log_factors(const or_scheme *s, int i, int j, int X, int role, or_lo
     }
 }
 
+/* The rest of an iteration of the additions objective, after try_flip found
+ * (i, j, X, role) among the flips that keep every factor non-zero.  Reading
+ * of the complexity-minimisation mode (Sec. 3.9: flips without reduction
+ * edges): apply the flip; the rank never changes, there is no reduce and no
+ * expand; Algorithm 1's best-scheme rule is applied to the number of
+ * non-zero coefficients (equivalently to the naive additions of Sec. 4.5,
+ * which differ from it by the constant 2r + mp): strictly fewer always, as
+ * many with probability t_eq (word 0 of block (t,0,1)); a strict improvement
+ * records (t, naive additions) and resets the plateau; then the plateau
+ * restart. */
+static void additions_step(or_walk *w, const or_params *prm, int64_t t, int i, int j, int X,
+                           int role)
+{
+    or_scheme *s = &w->cur;
+    or_flip(s, i, j, X, shared_sign(s, i, j, X), role);
+    w->c.flips++;
+    uint32_t g[4];
+    draw(prm->seed, t, 0, 1, g);
+    const long nnz = or_nonzeros(s);
+    if (nnz < w->best_nnz) {
+        set_best(w);
+        w->plateau_start = t;
+        if (w->n_rec < OR_MAXREC) {
+            w->rec_iter[w->n_rec] = t;
+            w->rec_rank[w->n_rec] = (int32_t)or_naive_additions(s);
+        }
+        w->n_rec++;
+        w->c.improvements++;
+    } else if (nnz == w->best_nnz && (uint64_t)g[0] < prm->t_eq) {
+        set_best(w);
+        w->c.eq_accepts++;
+    }
+    restart_check(w, prm, t);
+}
+
+/* the walk's stop rule: best rank (or, for the additions objective, best
+ * naive additions) at most the target */
+static int reached(const or_walk *w, const or_params *prm)
+{
+    if (prm->objective == 1)
+        return w->best_nnz - 2L * w->best.r - (long)w->best.m * w->best.p <= prm->target_rank;
+    return w->best_rank <= prm->target_rank;
+}
+
 /* One iteration of Algorithm 1.  choice < 0: uniform proposals (try_flip);
  * choice >= 0: the externally chosen attempt (255 = fallback), see
  * or_walk_run_choices.  Returns 0, or 1 when the choice was inconsistent. */
@@ -730,10 +802,20 @@ static int one_iteration(or_walk *w, const or_params *prm, int64_t t, int choice
         }
     }
     if (!found) {
-        /* Algorithm 1: no flip -> expand, continue */
+        /* Algorithm 1: no flip -> expand, continue (the additions objective
+         * keeps the rank and does not expand) */
         w->c.dead_ends++;
-        expand(w, prm, t);
+        if (prm->objective != 1) expand(w, prm, t);
         restart_check(w, prm, t);
+        if (lg) lg->rank_after = s->r;
+        return 0;
+    }
+    if (prm->objective == 1) {
+        if (lg) {
+            log_factors(s, i, j, X, role, lg);
+            lg->rank_before = s->r;
+        }
+        additions_step(w, prm, t, i, j, X, role);
         if (lg) lg->rank_after = s->r;
         return 0;
     }
@@ -765,8 +847,7 @@ static int one_iteration(or_walk *w, const or_params *prm, int64_t t, int choice
     draw(prm->seed, t, 0, 1, g);
     /* best update: strictly better always, equal rank with probability 0.01 */
     if (s->r < w->best_rank) {
-        w->best = *s;
-        w->best_rank = s->r;
+        set_best(w);
         w->plateau_start = t;
         if (w->n_rec < OR_MAXREC) {
             w->rec_iter[w->n_rec] = t;
@@ -775,7 +856,7 @@ static int one_iteration(or_walk *w, const or_params *prm, int64_t t, int choice
         w->n_rec++;
         w->c.improvements++;
     } else if (s->r == w->best_rank && (uint64_t)g[0] < prm->t_eq) {
-        w->best = *s;
+        set_best(w);
         w->c.eq_accepts++;
     }
     /* reduce with probability p_reduce: merge the modified terms */
@@ -797,9 +878,9 @@ int or_attempt_candidate(const or_scheme *s, uint64_t seed, int64_t t, int a, in
     draw(seed, t, (uint32_t)a, 0, rw);
     int i = uniform_below(rw[0], s->r);
     int X = uniform_below(rw[1], 3);
-    int n = attempt_candidates(s, i, X, -1, &j, &sg, &role);
+    int n = attempt_candidates(s, i, X, 0, -1, &j, &sg, &role);
     if (n == 0) return 0;
-    attempt_candidates(s, i, X, uniform_below(rw[2], n), &j, &sg, &role);
+    attempt_candidates(s, i, X, 0, uniform_below(rw[2], n), &j, &sg, &role);
     *pi = i; *pj = j; *pX = X; *prole = role;
     return n;
 }
@@ -808,7 +889,7 @@ void or_walk_run_logged(or_walk *w, const or_params *prm, int64_t n_iters, or_lo
                         int64_t log_cap, int32_t format_slot)
 {
     for (int64_t step = 0; step < n_iters; ++step) {
-        if (w->best_rank <= prm->target_rank) w->done = 1;
+        if (reached(w, prm)) w->done = 1;
         if (w->done || w->t >= prm->max_iters) return;
         int64_t t = w->t + 1;
         or_log *lg = (log && t <= log_cap) ? &log[t - 1] : NULL;
@@ -816,14 +897,14 @@ void or_walk_run_logged(or_walk *w, const or_params *prm, int64_t n_iters, or_lo
         if (lg) lg->format_slot = format_slot;
         w->t = t;
     }
-    if (w->best_rank <= prm->target_rank) w->done = 1;
+    if (reached(w, prm)) w->done = 1;
 }
 
 void or_walk_run_choices(or_walk *w, const or_params *prm, int64_t n_iters,
                          const uint8_t *choices, int64_t n_choices, int64_t *bad)
 {
     for (int64_t step = 0; step < n_iters; ++step) {
-        if (w->best_rank <= prm->target_rank) w->done = 1;
+        if (reached(w, prm)) w->done = 1;
         if (w->done || w->t >= prm->max_iters) return;
         int64_t t = w->t + 1;
         if (t > n_choices) return;
@@ -833,19 +914,19 @@ void or_walk_run_choices(or_walk *w, const or_params *prm, int64_t n_iters,
         }
         w->t = t;
     }
-    if (w->best_rank <= prm->target_rank) w->done = 1;
+    if (reached(w, prm)) w->done = 1;
 }
 
 void or_walk_run(or_walk *w, const or_params *prm, int64_t n_iters)
 {
     for (int64_t step = 0; step < n_iters; ++step) {
-        if (w->best_rank <= prm->target_rank) w->done = 1;
+        if (reached(w, prm)) w->done = 1;
         if (w->done || w->t >= prm->max_iters) return;
         int64_t t = w->t + 1;
         one_iteration(w, prm, t, -1, NULL);
         w->t = t;
     }
-    if (w->best_rank <= prm->target_rank) w->done = 1;
+    if (reached(w, prm)) w->done = 1;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -48,6 +48,7 @@ int  or_len(const or_scheme *s, int X);
 void or_standard(or_scheme *s, int m, int n, int p, int z2);
 long or_brent_violations(const or_scheme *s);
 long or_naive_additions(const or_scheme *s);
+long or_nonzeros(const or_scheme *s);
 void or_normalise_term(or_scheme *s, int l);
 int  or_is_normalised(const or_scheme *s);
 int  or_project(const or_scheme *in, int axis, int index, or_scheme *out);
@@ -67,6 +68,11 @@ typedef struct {
     uint64_t t_eq;          /* Bernoulli thresholds: event iff word < t       */
     uint64_t t_reduce;
     uint64_t t_expand;
+    int32_t  objective;     /* 0: rank (Algorithm 1); 1: naive additions at a
+                               fixed rank (the complexity-minimisation mode of
+                               Sec. 3.9); target_rank is then the target
+                               number of naive additions                      */
+    int32_t  pad;
 } or_params;
 
 typedef struct {
@@ -78,6 +84,8 @@ typedef struct {
     or_scheme cur, best, start;
     int32_t  best_rank;
     int32_t  done;
+    int32_t  best_nnz;       /* non-zero coefficients of the best scheme       */
+    int32_t  pad;
     int64_t  t;              /* iterations completed                          */
     int64_t  plateau_start;  /* iteration of the last strict improvement or restart */
     or_counters c;

@@ -27,7 +27,8 @@ class Params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("max_iters", C.c_int64), ("plateau", C.c_int64),
                 ("target_rank", C.c_int32), ("r_cap", C.c_int32), ("flip_tries", C.c_int32),
                 ("restart_from_best", C.c_int32), ("t_eq", C.c_uint64),
-                ("t_reduce", C.c_uint64), ("t_expand", C.c_uint64)]
+                ("t_reduce", C.c_uint64), ("t_expand", C.c_uint64), ("objective", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 COUNTER_NAMES = ("iters", "flips", "attempts", "fallbacks", "dead_ends", "zero_removed",
@@ -41,7 +42,8 @@ class Counters(C.Structure):
 
 class Walk(C.Structure):
     _fields_ = [("cur", Scheme), ("best", Scheme), ("start", Scheme),
-                ("best_rank", C.c_int32), ("done", C.c_int32), ("t", C.c_int64),
+                ("best_rank", C.c_int32), ("done", C.c_int32), ("best_nnz", C.c_int32),
+                ("pad", C.c_int32), ("t", C.c_int64),
                 ("plateau_start", C.c_int64), ("c", Counters), ("n_rec", C.c_int32),
                 ("rec_iter", C.c_int64 * MAXREC), ("rec_rank", C.c_int32 * MAXREC)]
 
@@ -63,6 +65,8 @@ def lib():
         L.or_brent_violations.restype = C.c_long
         L.or_naive_additions.argtypes = [P(Scheme)]
         L.or_naive_additions.restype = C.c_long
+        L.or_nonzeros.argtypes = [P(Scheme)]
+        L.or_nonzeros.restype = C.c_long
         L.or_normalise_term.argtypes = [P(Scheme), C.c_int]
         L.or_is_normalised.argtypes = [P(Scheme)]
         L.or_project.argtypes = [P(Scheme), C.c_int, C.c_int, P(Scheme)]
@@ -143,6 +147,10 @@ def naive_additions(s: Scheme) -> int:
     return int(lib().or_naive_additions(C.byref(s)))
 
 
+def nonzeros(s: Scheme) -> int:
+    return int(lib().or_nonzeros(C.byref(s)))
+
+
 def is_normalised(s: Scheme) -> bool:
     return bool(lib().or_is_normalised(C.byref(s)))
 
@@ -181,11 +189,11 @@ def copy(s: Scheme) -> Scheme:
 
 def make_params(seed=0, max_iters=100000, plateau=20000, target_rank=0, r_cap=None,
                 flip_tries=7, restart_from_best=0, t_eq=42949673, t_reduce=1 << 32,
-                t_expand=0, r0=None):
+                t_expand=0, r0=None, objective=0):
     if r_cap is None:
         r_cap = (r0 or 0) + 8
     return Params(seed, max_iters, plateau, target_rank, r_cap, flip_tries,
-                  restart_from_best, t_eq, t_reduce, t_expand)
+                  restart_from_best, t_eq, t_reduce, t_expand, objective, 0)
 
 
 def new_walk(start: Scheme) -> Walk:
