@@ -143,7 +143,23 @@ typedef struct {
     uint64_t t_eq;             /* accept an equal-rank scheme as best (Alg. 1: 0.01) */
     uint64_t t_reduce;         /* p_reduce of Alg. 1                              */
     uint64_t t_expand;         /* p_expand of Alg. 1                              */
+    int32_t  objective;        /* TSF_OBJ_RANK or TSF_OBJ_ADDITIONS               */
+    int32_t  reserved;
 } tsf_walk_params;
+
+/* Objectives of a walk.  TSF_OBJ_RANK: Algorithm 1 (the focused search of
+ * Sec. 3.9).  TSF_OBJ_ADDITIONS: the complexity-minimisation mode of Sec. 3.9
+ * (flips without reduction edges), scored by the naive additions of Sec. 4.5
+ * (non-zero coefficients - 2r - mp): only flips that leave both modified
+ * factors non-zero are candidates, so the rank never changes; there is no
+ * reduce and no expand; the best scheme is replaced when the current one has
+ * strictly fewer non-zero coefficients, or as many with probability t_eq; a
+ * strict improvement is recorded (with its naive additions in the record's
+ * rank field) and resets the plateau counter; the walk stops once the best
+ * scheme's naive additions are at most target_rank.  t_reduce and t_expand
+ * are ignored. */
+#define TSF_OBJ_RANK 0
+#define TSF_OBJ_ADDITIONS 1
 
 /* Per-walk state header (device memory, one per walk, 160 bytes). */
 typedef struct {
@@ -157,7 +173,7 @@ typedef struct {
                                   not fit the batch; -2 invalid start scheme      */
     int32_t n_rec;             /* strict improvements so far (records kept up to
                                   the batch's rec_cap)                            */
-    int32_t reserved;
+    int32_t best_nnz;          /* non-zero coefficients of the best scheme        */
     int64_t t;                 /* iterations completed                            */
     int64_t plateau_start;     /* iteration of the last strict improvement/restart */
     int64_t counters[12];      /* iters, flips, attempts, fallbacks, dead_ends,
@@ -165,10 +181,11 @@ typedef struct {
                                   restarts, eq_accepts, improvements              */
 } tsf_walk_header;
 
-/* One strict improvement of a walk's best rank. */
+/* One strict improvement of a walk's best rank (TSF_OBJ_ADDITIONS: of its
+ * best naive additions). */
 typedef struct {
     int64_t iter;              /* iteration at which it happened                 */
-    int32_t rank;              /* the new best rank                              */
+    int32_t rank;              /* the new best rank (or naive additions)         */
     int32_t reserved;
 } tsf_record;
 

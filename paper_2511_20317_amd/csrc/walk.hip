@@ -50,12 +50,18 @@ __global__ void __launch_bounds__(64) init_kernel(tsf_walk_header *hdr, uint64_t
         }
     }
     const bool any_bad = __ballot(bad) != 0;
+    // non-zero coefficients of the start scheme
+    int nnz = 0;
+    if (ok)
+        for (int k = lane; k < r0; k += 64)
+            for (int X = 0; X < 3; ++X) nnz += __builtin_popcountll(start[base + k * 6 + 2 * X]);
+    for (int off = 32; off > 0; off >>= 1) nnz += __shfl_xor(nnz, off);
     if (lane == 0) {
         h->done = (!ok || any_bad) ? -2 : 0;
         h->rank = r0;
         h->best_rank = r0;
         h->n_rec = 0;
-        h->reserved = 0;
+        h->best_nnz = nnz;
         h->t = 0;
         h->plateau_start = 0;
         for (int c = 0; c < 12; ++c) h->counters[c] = 0;
@@ -409,6 +415,8 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (prm->t_eq > (1ull << 32) || prm->t_reduce > (1ull << 32) || prm->t_expand > (1ull << 32))
         return tsf_fail(TSF_E_ARG, "a probability threshold exceeds 2^32");
     if (n_iters < 0) return tsf_fail(TSF_E_ARG, "n_iters < 0");
+    if (prm->objective != TSF_OBJ_RANK && prm->objective != TSF_OBJ_ADDITIONS)
+        return tsf_fail(TSF_E_ARG, "objective %d", prm->objective);
     if (b->log && b->log_cap < 0) return tsf_fail(TSF_E_ARG, "log_cap < 0");
     int strategy = launch ? launch->strategy : 0;
     if (strategy < 0 || strategy > 3) return tsf_fail(TSF_E_ARG, "strategy %d not in 0..3", strategy);
@@ -455,6 +463,7 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     a.t_expand = prm->t_expand;
     a.flip_tries = prm->flip_tries;
     a.restart_from_best = prm->restart_from_best;
+    a.objective = prm->objective;
     a.n_walks = b->n_walks;
     a.cap = b->capacity;
     a.rec_cap = b->rec_cap;
@@ -611,6 +620,8 @@ tsf_status tsf_walk_learned(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_
     if (la.strategy == 0) la.strategy = 1;
     if (la.strategy != 1)
         return tsf_fail(TSF_E_ARG, "learned proposals use the attempt-parallel strategy 1");
+    if (prm && prm->objective != TSF_OBJ_RANK)
+        return tsf_fail(TSF_E_ARG, "learned proposals serve the rank objective only");
     tsf_status st = prepare_walk(prm, b, n_iters, &la, a, L);
     if (st) return st;
     if (!L.ap)

@@ -54,6 +54,7 @@ struct KArgs {
     uint64_t t_eq, t_reduce, t_expand;
     int32_t flip_tries;
     int32_t restart_from_best;
+    int32_t objective;  // TSF_OBJ_RANK or TSF_OBJ_ADDITIONS
     int32_t n_walks;
     int32_t cap;
     int32_t rec_cap;
@@ -162,6 +163,10 @@ struct Walker {
     // walk scalars, identical in every lane of the group
     uint64_t seed;
     int r, r_cap, best_rank, start_rank, target, n_rec;
+    // additions objective: flips must keep every factor non-zero, the best
+    // scheme is the one with the fewest non-zero coefficients
+    bool additions;
+    int nnz, best_nnz, mp;
     int64_t t, plateau_start;
     uint32_t cnt[C_NUM];
     const KArgs *a;
@@ -480,10 +485,14 @@ struct Walker {
             lg->rank_before = r;
         }
         TV<T> ny, nz;
-        axpy(sg, ld(i, Y), ld(j, Y), ny);
-        axpy(-1, ld(j, Z), ld(i, Z), nz);
+        const TV<T> yi = ld(i, Y), zj0 = ld(j, Z);
+        axpy(sg, yi, ld(j, Y), ny);
+        axpy(-1, zj0, ld(i, Z), nz);
         zi = ny.d == 0;
         zj = nz.d == 0;
+        if (additions)
+            nnz += popc64((uint64_t)ny.d) - popc64((uint64_t)yi.d) + popc64((uint64_t)nz.d) -
+                   popc64((uint64_t)zj0.d);
         if constexpr (!Z2) {
             // Sec. 3.6: a u or v factor whose first non-zero entry is -1 is
             // negated, and w absorbs the sign
@@ -563,8 +572,9 @@ struct Walker {
                         TV<T> o1, o2;
                         const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
                         const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
-                        v0 = a1 && b1;
-                        v1 = a2 && b2;
+                        const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
+                        v0 = a1 && b1 && keep;
+                        v1 = a2 && b2 && keep;
                     }
                 }
             }
@@ -634,8 +644,11 @@ struct Walker {
             TV<T> o1, o2;
             const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
             const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
-            m0 |= (uint64_t)(a1 && b1) << kk;
-            m1 |= (uint64_t)(a2 && b2) << kk;
+            // a valid sum or difference is zero exactly when the supports
+            // agree; the additions objective admits no such flip
+            const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
+            m0 |= (uint64_t)(a1 && b1 && keep) << kk;
+            m1 |= (uint64_t)(a2 && b2 && keep) << kk;
         }
     }
 
@@ -1013,11 +1026,38 @@ struct Walker {
             r = keep;
         }
     }
-    __device__ void store_scheme(uint64_t *dst) const
+    // writes the current scheme to HBM; returns its non-zero coefficients
+    __device__ int store_scheme(uint64_t *dst) const
     {
+        int c = 0;
         for (int k = gl; k < r; k += G)
 #pragma unroll
-            for (int x = 0; x < 6; ++x) dst[k * 6 + x] = (uint64_t)lds[idx(k, x >> 1) + (x & 1)];
+            for (int x = 0; x < 6; ++x) {
+                const T v = lds[idx(k, x >> 1) + (x & 1)];
+                dst[k * 6 + x] = (uint64_t)v;
+                if ((x & 1) == 0) c += popc64((uint64_t)v);
+            }
+        return group_sum(c);
+    }
+    __device__ int count_nnz() const
+    {
+        int c = 0;
+        for (int k = gl; k < r; k += G)
+#pragma unroll
+            for (int X = 0; X < 3; ++X) c += popc64((uint64_t)ld(k, X).d);
+        return group_sum(c);
+    }
+    __device__ __forceinline__ int group_sum(int c) const
+    {
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, G);
+        return c;
+    }
+    // the stop rule: best rank (additions objective: best naive additions,
+    // non-zero coefficients - 2r - mp, Sec. 4.5) at most the target
+    __device__ __forceinline__ bool reached() const
+    {
+        return additions ? best_nnz - 2 * best_rank - mp <= target : best_rank <= target;
     }
 
     __device__ void restart_check()
@@ -1029,6 +1069,7 @@ struct Walker {
             const int rr = from_best ? best_rank : start_rank;
             load_scheme(src, rr);
             r = rr;
+            if (additions) nnz = count_nnz();
             plateau_start = t;
             cnt[C_RESTARTS]++;
         }
@@ -1047,14 +1088,40 @@ struct Walker {
     __device__ void finish_iteration(bool found, int fi, int fj)
     {
         if (!found) {
-            // Algorithm 1: no flip -> expand, continue
+            // Algorithm 1: no flip -> expand, continue (the additions
+            // objective keeps the rank and does not expand)
             cnt[C_DEAD_ENDS]++;
-            expand();
+            if (!additions) expand();
             restart_check();
             write_log(false);
             return;
         }
         cnt[C_FLIPS]++;
+        if (additions) {
+            // the rank is unchanged: best by non-zero count, no reduce or expand
+            const uint32_t g0 = from_lane(pb.x[0], G - 1);
+            if (nnz < best_nnz) {
+                store_scheme(a->best + (size_t)walk * a->cap * 6);
+                best_nnz = nnz;
+                best_rank = r;
+                plateau_start = t;
+                if (gl == 0 && n_rec < a->rec_cap) {
+                    tsf_record *rc = a->rec + (size_t)walk * a->rec_cap + n_rec;
+                    rc->iter = t;
+                    rc->rank = nnz - 2 * r - mp;
+                    rc->reserved = 0;
+                }
+                n_rec++;
+                cnt[C_IMPROVEMENTS]++;
+            } else if (nnz == best_nnz && (uint64_t)g0 < a->t_eq) {
+                store_scheme(a->best + (size_t)walk * a->cap * 6);
+                best_rank = r;
+                cnt[C_EQ_ACCEPTS]++;
+            }
+            restart_check();
+            write_log(true);
+            return;
+        }
         int tr0 = fi, tr1 = fj;
         const bool zi = zfi, zj = zfj;
         if (zi && zj) {
@@ -1073,7 +1140,7 @@ struct Walker {
         const uint32_t g1 = from_lane(pb.x[1], G - 1);
         const uint32_t g2 = from_lane(pb.x[2], G - 1);
         if (r < best_rank) {
-            store_scheme(a->best + (size_t)walk * a->cap * 6);
+            best_nnz = store_scheme(a->best + (size_t)walk * a->cap * 6);
             best_rank = r;
             plateau_start = t;
             if (gl == 0 && n_rec < a->rec_cap) {
@@ -1085,7 +1152,7 @@ struct Walker {
             n_rec++;
             cnt[C_IMPROVEMENTS]++;
         } else if (r == best_rank && (uint64_t)g0 < a->t_eq) {
-            store_scheme(a->best + (size_t)walk * a->cap * 6);
+            best_nnz = store_scheme(a->best + (size_t)walk * a->cap * 6);
             cnt[C_EQ_ACCEPTS]++;
         }
         if ((uint64_t)g1 < a->t_reduce) cnt[C_MERGES] += (uint32_t)reduce(tr0, tr1);
@@ -1205,8 +1272,12 @@ __device__ __forceinline__ int flen(int m, int n, int p, int X)
     return X == 0 ? m * n : X == 1 ? n * p : p * m;
 }
 
+// The indexed kernels with 32-bit masks and 8 or more lanes per walk are held
+// to 168 VGPRs, which keeps three wavefronts per SIMD (they fit it without
+// spilling; the 64-bit ones do not).
 template <int G, int S, typename T, bool Z2, bool AP, bool IX>
-__global__ void __launch_bounds__(256) walk_kernel(KArgs a)
+__global__ void __launch_bounds__(256) __attribute__((
+    amdgpu_waves_per_eu((IX && G >= 8 && sizeof(T) == 4) ? 3 : 1))) walk_kernel(KArgs a)
 {
     extern __shared__ uint64_t smem_u64[];
     T *smem = reinterpret_cast<T *>(smem_u64);
@@ -1245,6 +1316,10 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
     wk.r = h->rank;
     wk.r_cap = h->r_cap;
     wk.best_rank = h->best_rank;
+    wk.best_nnz = h->best_nnz;
+    wk.mp = m * p;
+    wk.additions = a.objective == TSF_OBJ_ADDITIONS;
+    wk.nnz = 0;
     wk.start_rank = h->start_rank;
     wk.target = h->target_rank;
     wk.n_rec = h->n_rec;
@@ -1255,36 +1330,38 @@ __global__ void __launch_bounds__(256) walk_kernel(KArgs a)
     wk.logging = false;
     wk.fmt_slot = format_slot(m, n, p);
     wk.load_scheme(a.cur + (size_t)walk * a.cap * 6, wk.r);
+    if (wk.additions) wk.nnz = wk.count_nnz();
 
     if constexpr (AP && !IX) {
         if (a.phase == 1) {
             // learned proposal, phase 1: candidates and feature rows only
-            if (wk.best_rank <= wk.target || wk.t >= a.max_iters) return;
+            if (wk.reached() || wk.t >= a.max_iters) return;
             wk.t += 1;
             wk.propose();
             return;
         }
     }
     if (AP && !IX && a.phase == 2) {
-        if (wk.best_rank <= wk.target) done = 1;
+        if (wk.reached()) done = 1;
         if (!done && wk.t < a.max_iters) {
             wk.t += 1;
             if constexpr (AP && !IX) wk.apply_learned();
         }
     } else {
         for (int64_t it = 0; it < a.n_iters; ++it) {
-            if (wk.best_rank <= wk.target) done = 1;
+            if (wk.reached()) done = 1;
             if (done || wk.t >= a.max_iters) break;
             wk.t += 1;
             wk.iteration();
         }
     }
-    if (wk.best_rank <= wk.target) done = 1;
+    if (wk.reached()) done = 1;
 
     wk.store_scheme(a.cur + (size_t)walk * a.cap * 6);
     if (wk.gl == 0) {
         h->rank = wk.r;
         h->best_rank = wk.best_rank;
+        h->best_nnz = wk.best_nnz;
         h->done = done;
         h->n_rec = wk.n_rec;
         h->t = wk.t;

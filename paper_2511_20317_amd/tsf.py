@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libtsf.so")
 
 TSF_TERNARY = 0
 TSF_Z2 = 1
+OBJ_RANK = 0
+OBJ_ADDITIONS = 1
 ALWAYS = 1 << 32                # Bernoulli threshold of probability 1
 EQ_ACCEPT = 42949673            # round(0.01 * 2^32): Algorithm 1's 1% equal-rank acceptance
 
@@ -46,7 +48,8 @@ class WalkParams(C.Structure):
     _fields_ = [("base_seed", C.c_uint64), ("first_walk_id", C.c_int64),
                 ("max_iters", C.c_int64), ("plateau", C.c_int64), ("flip_tries", C.c_int32),
                 ("restart_from_best", C.c_int32), ("t_eq", C.c_uint64),
-                ("t_reduce", C.c_uint64), ("t_expand", C.c_uint64)]
+                ("t_reduce", C.c_uint64), ("t_expand", C.c_uint64), ("objective", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class WalkBatchC(C.Structure):
@@ -80,7 +83,7 @@ MLP_IN, MLP_HID, MLP_NPARAM, MLP_NBF16 = 512, 256, 197380, 262400
 HEADER_DTYPE = np.dtype([("m", "<i4"), ("n", "<i4"), ("p", "<i4"), ("mode", "<i4"),
                          ("r_cap", "<i4"), ("target_rank", "<i4"), ("rank", "<i4"),
                          ("best_rank", "<i4"), ("start_rank", "<i4"), ("done", "<i4"),
-                         ("n_rec", "<i4"), ("reserved", "<i4"), ("t", "<i8"),
+                         ("n_rec", "<i4"), ("best_nnz", "<i4"), ("t", "<i8"),
                          ("plateau_start", "<i8"), ("counters", "<i8", (12,))])
 assert HEADER_DTYPE.itemsize == 160
 RECORD_DTYPE = np.dtype([("iter", "<i8"), ("rank", "<i4"), ("reserved", "<i4")])
@@ -271,9 +274,12 @@ def unpack(packed, m, n, p, rank, mode=TSF_TERNARY) -> Scheme:
 # walks on the GPU
 # ---------------------------------------------------------------------------
 def walk_params(base_seed=0, first_walk_id=0, max_iters=100000, plateau=20000, flip_tries=7,
-                restart_from_best=0, t_eq=EQ_ACCEPT, t_reduce=ALWAYS, t_expand=0):
+                restart_from_best=0, t_eq=EQ_ACCEPT, t_reduce=ALWAYS, t_expand=0,
+                objective=0):
+    """objective: OBJ_RANK (Algorithm 1) or OBJ_ADDITIONS (naive additions at a
+    fixed rank; target_rank of the batch is then the target additions)."""
     return WalkParams(base_seed, first_walk_id, max_iters, plateau, flip_tries,
-                      restart_from_best, t_eq, t_reduce, t_expand)
+                      restart_from_best, t_eq, t_reduce, t_expand, objective, 0)
 
 
 class Context:

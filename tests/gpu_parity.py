@@ -16,7 +16,7 @@ def oracle_start(scheme: tsf.Scheme):
 def oracle_params(prm: tsf.WalkParams, walk_id: int, r_cap: int, target: int):
     return O.Params(prm.base_seed + prm.first_walk_id + walk_id, prm.max_iters, prm.plateau,
                     target, r_cap, prm.flip_tries, prm.restart_from_best, prm.t_eq,
-                    prm.t_reduce, prm.t_expand)
+                    prm.t_reduce, prm.t_expand, prm.objective, 0)
 
 
 def run_oracle(groups, prm, walks, n_iters, splits=None, threads=8):
@@ -50,11 +50,11 @@ def compare(batch: tsf.WalkBatch, oracle_walks, label=""):
         got = {
             "t": int(h["t"]), "rank": int(h["rank"]), "best_rank": int(h["best_rank"]),
             "done": int(h["done"]), "plateau_start": int(h["plateau_start"]),
-            "n_rec": int(h["n_rec"]),
+            "n_rec": int(h["n_rec"]), "best_nnz": int(h["best_nnz"]),
         }
         want = {
             "t": ow.t, "rank": ow.cur.r, "best_rank": ow.best_rank, "done": ow.done,
-            "plateau_start": ow.plateau_start, "n_rec": ow.n_rec,
+            "plateau_start": ow.plateau_start, "n_rec": ow.n_rec, "best_nnz": ow.best_nnz,
         }
         if got != want:
             mism.append((tag, "header", got, want))

@@ -233,3 +233,51 @@ def test_autotune_leaves_state_and_keeps_parity(ctx):
     b.walk(ctx, prm, 2500)  # default launch -> the tuned configuration
     _sync()
     compare(b, run_oracle(groups, prm, range(0, 512, 7), 3000), "autotuned")
+
+
+# ------------------------------------------------------- additions objective
+def _oracle_rank_scheme(fmt, target, seed, z2=False):
+    """A scheme of the given rank found by the oracle's own rank walk (no GPU
+    output is an input of these tests)."""
+    from oracle import pyoracle as O
+    m, n, p = fmt
+    prm = O.make_params(seed=seed, max_iters=300000, plateau=30000, target_rank=target,
+                        r0=m * n * p)
+    w = O.new_walk(O.standard(m, n, p, z2=z2))
+    O.run(w, prm, 300000)
+    assert w.best_rank == target
+    d = O.from_c(w.best)
+    return tsf.Scheme(m, n, p, d["U"], d["V"], d["W"], mode=tsf.TSF_Z2 if z2 else tsf.TSF_TERNARY)
+
+
+@pytest.fixture(scope="module")
+def ranked_schemes():
+    return {"223": _oracle_rank_scheme((2, 2, 3), 11, 2),
+            "233": _oracle_rank_scheme((2, 3, 3), 18, 2),
+            "333": _oracle_rank_scheme((3, 3, 3), 25, 0),
+            "223z2": _oracle_rank_scheme((2, 2, 3), 11, 4, z2=True)}
+
+
+@pytest.mark.parametrize("strategy,lanes", [(1, 8), (2, 16), (3, 8), (3, 16)])
+def test_additions_objective(ctx, ranked_schemes, strategy, lanes):
+    """The naive-additions objective from schemes of reduced rank: bit-exact
+    with the oracle, rank constant, one group stops at its additions target."""
+    s = ranked_schemes
+    from oracle import pyoracle as O
+    a223 = O.naive_additions(O.to_c(*s["223"].live(), 2, 2, 3))
+    groups = [(s["223"], 16, 16, a223 - 8), (s["233"], 16, 24, 0), (s["333"], 16, 33, 0)]
+    prm = tsf.walk_params(base_seed=13, max_iters=4000, plateau=1500, objective=tsf.OBJ_ADDITIONS)
+    b = _run(ctx, groups, prm, 4000, splits=[1500, 2500], lanes=lanes, strategy=strategy)
+    compare(b, run_oracle(groups, prm, range(48), 4000), "additions s=%d G=%d" % (strategy, lanes))
+    hdr = b.headers()
+    assert (hdr["rank"] == hdr["start_rank"]).all() and (hdr["best_rank"] == hdr["start_rank"]).all()
+    assert (hdr["done"][:16] == 1).any()
+    assert (b.verify_device(which=1).cpu().numpy() == 0).all()
+
+
+@pytest.mark.parametrize("strategy", [2, 3])
+def test_additions_objective_z2(ctx, ranked_schemes, strategy):
+    groups = [(ranked_schemes["223z2"], 32, 16, 0)]
+    prm = tsf.walk_params(base_seed=17, max_iters=3000, plateau=1000, objective=tsf.OBJ_ADDITIONS)
+    b = _run(ctx, groups, prm, 3000, strategy=strategy, lanes=16)
+    compare(b, run_oracle(groups, prm, range(32), 3000), "additions z2 s=%d" % strategy)
