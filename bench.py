@@ -250,6 +250,56 @@ def run_large(ctx, args):
             "phases": phases, "invalid_after_meta": int((hb["done"] < 0).sum())}
 
 
+def run_additions(ctx, args):
+    """The complexity-minimisation mode on (3,3,3): a focused rank search of
+    65,536 walks (2e5 iterations, untimed) leaves every walk a best scheme of
+    rank 23..26; each is copied on the GPU into a new batch as its start and
+    walked with the naive-additions objective (timed): flips/s and the naive
+    additions (non-zero coefficients - 2r - mp) before and after, per rank."""
+    import torch
+    from paper_2511_20317_amd import tsf
+    n = args.walks
+    focus = tsf.WalkBatch([(tsf.init_scheme(3, 3, 3), n, 35, 23)], rec_cap=8)
+    focus.init(ctx)
+    prm0 = tsf.walk_params(base_seed=0, max_iters=200000, plateau=50000)
+    for _ in range(2):
+        focus.walk(ctx, prm0, 100000)
+    torch.cuda.synchronize()
+    batch = tsf.WalkBatch.empty(n, focus.capacity, tsf.TSF_TERNARY, max_len=9, rec_cap=32)
+    batch.meta_from(focus, 1, np.zeros(n), np.zeros(n), np.zeros(n), r_cap_extra=0)
+    batch.init(ctx)
+    batch.hdr.view(torch.int32).view(n, 40)[:, 5] = 0   # target additions: none
+    h0 = batch.headers()
+    start_add = h0["best_nnz"] - 2 * h0["start_rank"] - 9
+    prm = tsf.walk_params(base_seed=1 << 40, max_iters=10 ** 9, plateau=50000,
+                          objective=tsf.OBJ_ADDITIONS)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for k in range(args.steps):
+        batch.walk(ctx, prm, args.iters)
+        print("additions step %d/%d" % (k + 1, args.steps), file=sys.stderr, flush=True)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h = batch.headers()
+    nv = batch.verify_device(1).cpu().numpy()
+    best_add = h["best_nnz"] - 2 * h["best_rank"] - 9
+    per_rank = {}
+    for r in sorted(set(h["start_rank"].tolist())):
+        sel = h["start_rank"] == r
+        per_rank[str(r)] = {"walks": int(sel.sum()),
+                            "start_additions_min": int(start_add[sel].min()),
+                            "start_additions_median": float(np.median(start_add[sel])),
+                            "best_additions_min": int(best_add[sel].min()),
+                            "best_additions_median": float(np.median(best_add[sel]))}
+    flips = int(h["counters"][:, 1].sum())
+    return {"flips_per_s": flips / wall, "walk_kernel_ms": e0.elapsed_time(e1), "wall_s": wall,
+            "rank_kept": bool((h["rank"] == h["start_rank"]).all()),
+            "best_schemes_failing_brent": int((nv != 0).sum()), "by_start_rank": per_rank}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,8 +317,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=100000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter scale)")
-    ap.add_argument("--workload", default="333", choices=["333", "mixed", "large"],
-                    help="333: the (3,3,3) benchmark; mixed / large: the other workloads")
+    ap.add_argument("--workload", default="333", choices=["333", "mixed", "large", "additions"],
+                    help="333: the (3,3,3) benchmark; mixed / large / additions: the other "
+                         "workloads")
     ap.add_argument("--learned", action="store_true",
                     help="also train the proposal network and compare it with uniform proposals")
     ap.add_argument("--learn-walks", type=int, default=2048)
@@ -290,18 +341,23 @@ def main():
     torch.cuda.set_device(0)
     ctx = tsf.Context()
     if args.workload != "333":
-        res = run_mixed(ctx, args) if args.workload == "mixed" else run_large(ctx, args)
+        res = {"mixed": run_mixed, "large": run_large,
+               "additions": run_additions}[args.workload](ctx, args)
         if args.workload == "mixed":
             value = res["ternary"]["flips_per_s"]
             desc = ("131,072 walks over (3,3,4), (3,4,5), (4,4,4), (4,4,5) in one launch, "
                     "ternary then Z2")
+        elif args.workload == "additions":
+            value = res["flips_per_s"]
+            desc = ("65,536 (3,3,3) walks minimising naive additions at fixed rank from the best "
+                    "schemes of a 2e5-iteration rank search")
         else:
             value = res["flips_per_s"]
             desc = ("98,304 walks over (4,5,12), (5,6,10), (6,7,9) with device project to "
                     "p-1 and extend back between rounds")
         out = {"metric": "flips/sec on 1 GPU", "value": value, "unit": "flips/s", "n_gpus": 1,
                "steps": args.steps, "warmup": 0, "higher_is_better": True, "scaling": "weak",
-               "vs_baseline": None, "dtype": "u32" if args.workload == "mixed" else "u64",
+               "vs_baseline": None, "dtype": "u64" if args.workload == "large" else "u32",
                "data": "synthetic", "config": {"workload": desc, "walks": args.walks,
                                                "iters_per_step": args.iters},
                "results": res}
