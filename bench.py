@@ -295,9 +295,23 @@ def run_additions(ctx, args):
                             "best_additions_min": int(best_add[sel].min()),
                             "best_additions_median": float(np.median(best_add[sel]))}
     flips = int(h["counters"][:, 1].sum())
+    # isotropy invariants (Sec. 3.7) of every best scheme on the GPU, and the
+    # number of distinct type polynomials among those of the lowest rank
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record()
+    ranks, sums = batch.invariants(which=1)
+    e3.record()
+    e3.synchronize()
+    low = int(h["best_rank"].min())
+    sel = np.flatnonzero(h["best_rank"] == low)
+    rk = ranks.cpu().numpy()[sel, :low]
+    types = {tuple(sorted(map(tuple, r.tolist()))) for r in rk}
     return {"flips_per_s": flips / wall, "walk_kernel_ms": e0.elapsed_time(e1), "wall_s": wall,
             "rank_kept": bool((h["rank"] == h["start_rank"]).all()),
-            "best_schemes_failing_brent": int((nv != 0).sum()), "by_start_rank": per_rank}
+            "best_schemes_failing_brent": int((nv != 0).sum()), "by_start_rank": per_rank,
+            "invariants": {"kernel_ms": e2.elapsed_time(e3), "schemes": n,
+                           "lowest_rank": low, "schemes_at_lowest_rank": int(sel.size),
+                           "distinct_type_polynomials": len(types)}}
 
 
 def main():

@@ -115,6 +115,28 @@ tsf_status tsf_meta_project(const tsf_scheme *in, int32_t axis, int32_t index, t
  * Errors: TSF_E_ARG, TSF_E_FORMAT (a new length > 64), TSF_E_CAPACITY. */
 tsf_status tsf_meta_extend(const tsf_scheme *in, int32_t axis, tsf_scheme *out);
 
+/* Isotropy invariants (Sec. 3.7).  Each factor of term l is read as a matrix
+ * (u: m x n, entry a_ij at row i, column j; v: n x p; w: p x m, entry c_ik at
+ * row k, column i) and its rank taken over Q for ternary schemes, over GF(2)
+ * for Z2 schemes; (a_l, b_l, c_l) are the ranks of term l's three factors
+ * (each at most 8, since a factor has at most 64 entries).
+ *   type polynomial      sum_l X^a_l Y^b_l Z^c_l        -> type_poly[a][b][c]
+ *   symmetric polynomial sum over the permutations pi of (x,y,z) of
+ *                        pi(sum_l x^a_l y^b_l z^c_l)    -> sym_poly[a][b][c]
+ *   rank-sum polynomial  w^(sum a_l) + w^(sum b_l) + w^(sum c_l)
+ *                                                        -> rank_sum[0..2]
+ * (coefficients of the monomials; rank_sum holds the three exponents). */
+typedef struct {
+    int32_t rank_sum[3];
+    int32_t type_poly[9][9][9];
+    int32_t sym_poly[9][9][9];
+} tsf_invariants;
+
+/* Invariants of one scheme (host).  term_ranks (optional, host, rank x 3
+ * bytes) receives (a_l, b_l, c_l) per term.
+ * Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_NOT_TERNARY. */
+tsf_status tsf_scheme_invariants(const tsf_scheme *s, uint8_t *term_ranks, tsf_invariants *out);
+
 /* int8 interchange <-> packed one-bit form (Sec. 3.5.1), host memory.
  * tsf_pack writes in->d.capacity terms (48 bytes each; rows >= rank zero).
  * tsf_unpack reads d->capacity packed terms into out (whose d is set to *d).
@@ -298,6 +320,16 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
  * Errors: TSF_E_ARG, TSF_E_DEVICE. */
 tsf_status tsf_verify_batch(const tsf_walk_batch *b, int32_t which, int64_t *n_violated,
                             void *hip_stream);
+
+/* Isotropy invariants (Sec. 3.7, see tsf_scheme_invariants) of the current
+ * (which = 0), best (1) or start (2) scheme of every walk, on the GPU:
+ * term_ranks (device, n_walks x capacity x 3 bytes) receives the factor ranks
+ * (a_l, b_l, c_l) of each live term (slots past the scheme's rank are left
+ * unchanged), rank_sums (device, n_walks x 3 int32) the three sums.  A walk
+ * whose header does not fit the batch gets rank_sums -1.  Async on the
+ * stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
+tsf_status tsf_invariants_batch(const tsf_walk_batch *b, int32_t which, uint8_t *term_ranks,
+                                int32_t *rank_sums, void *hip_stream);
 
 /* Meta operators (Sec. 3.3.2) on every walk of a batch at once, on the GPU:
  * the current (which = 0) or best (which = 1) scheme of walk w of `in`

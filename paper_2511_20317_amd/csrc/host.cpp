@@ -387,6 +387,32 @@ tsf_status tsf_pack(const tsf_scheme *in, uint64_t *packed)
     return TSF_OK;
 }
 
+tsf_status tsf_scheme_invariants(const tsf_scheme *s, uint8_t *term_ranks, tsf_invariants *out)
+{
+    if (!s || !out || !s->U || !s->V || !s->W) return fail(TSF_E_ARG, "null argument");
+    tsf_status st = check_dims(s->d);
+    if (st) return st;
+    std::vector<Term> t;
+    if ((st = to_terms(s, t))) return st;
+    const int m = s->d.m, n = s->d.n, p = s->d.p;
+    const int rows[3] = {m, n, p}, cols[3] = {n, p, m};
+    const bool z2 = s->d.mode == TSF_Z2;
+    std::memset(out, 0, sizeof *out);
+    int32_t M[64];
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (size_t l = 0; l < t.size(); ++l) {
+        int rk[3];
+        for (int X = 0; X < 3; ++X) {
+            rk[X] = factor_rank(t[l].f[2 * X], t[l].f[2 * X + 1], rows[X], cols[X], z2, M);
+            out->rank_sum[X] += rk[X];
+            if (term_ranks) term_ranks[3 * l + X] = (uint8_t)rk[X];
+        }
+        out->type_poly[rk[0]][rk[1]][rk[2]]++;
+        for (const int *q : perm) out->sym_poly[rk[q[0]]][rk[q[1]]][rk[q[2]]]++;
+    }
+    return TSF_OK;
+}
+
 tsf_status tsf_unpack(const uint64_t *packed, const tsf_dims *d, tsf_scheme *out)
 {
     if (!packed || !d || !out || !out->U || !out->V || !out->W)

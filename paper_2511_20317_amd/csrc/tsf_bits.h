@@ -134,3 +134,46 @@ TSF_HD int format_slot(int m, int n, int p)
     default: return 15;
     }
 }
+
+// Rank of one factor as a matrix (Sec. 3.7): entry (i, j) of the rows x cols
+// matrix is bit i*cols + j of the one-bit masks (d, s) -- u as m x n, v as
+// n x p, w as p x m (the C^T layout of Sec. 3.1).  Ternary factors are
+// reduced over GF(65521): a non-zero minor of order k <= 8 of a {-1,0,1}
+// matrix has |det| <= k^(k/2) <= 4096 (Hadamard's bound) < 65521, so this is
+// the rank over Q; Z2 factors are reduced over GF(2).  Fraction-free row
+// elimination (a row is replaced by pivot * row - row[c] * pivot_row, which
+// keeps the row space's dimension).  M: rows * cols int32 of scratch.
+TSF_HD int factor_rank(uint64_t d, uint64_t s, int rows, int cols, bool z2, int32_t *M)
+{
+    const uint32_t P = z2 ? 2u : 65521u;
+    for (int e = 0; e < rows * cols; ++e)
+        M[e] = ((d >> e) & 1) ? (((s >> e) & 1) ? (int32_t)(P - 1) : 1) : 0;
+    int rank = 0;
+    for (int c = 0; c < cols && rank < rows; ++c) {
+        int piv = -1;
+        for (int r = rank; r < rows; ++r)
+            if (M[r * cols + c] != 0) {
+                piv = r;
+                break;
+            }
+        if (piv < 0) continue;
+        if (piv != rank)
+            for (int x = 0; x < cols; ++x) {
+                const int32_t tmp = M[piv * cols + x];
+                M[piv * cols + x] = M[rank * cols + x];
+                M[rank * cols + x] = tmp;
+            }
+        const uint32_t pv = (uint32_t)M[rank * cols + c];
+        for (int r = rank + 1; r < rows; ++r) {
+            const uint32_t f = (uint32_t)M[r * cols + c];
+            if (f == 0) continue;
+            for (int x = c; x < cols; ++x) {
+                const uint32_t a = (uint32_t)M[r * cols + x] * pv % P;
+                const uint32_t b = (uint32_t)M[rank * cols + x] * f % P;
+                M[r * cols + x] = (int32_t)((a + P - b) % P);
+            }
+        }
+        ++rank;
+    }
+    return rank;
+}

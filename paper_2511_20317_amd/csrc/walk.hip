@@ -251,6 +251,55 @@ __global__ void __launch_bounds__(256) features_kernel(const tsf_flip_log *log, 
     write_feature_row(X + q * 512, f, slot, lg.rank_before);
 }
 
+// Isotropy invariants (Sec. 3.7) of one scheme per wavefront: lane l takes
+// terms l, l+64, ...; the rank of each factor comes from elimination in the
+// lane's own 64-word slice of LDS (factor_rank, shared with the host).
+__global__ void __launch_bounds__(64) invariants_kernel(const tsf_walk_header *hdr,
+                                                       const uint64_t *schemes, int32_t cap,
+                                                       int32_t n_walks, int32_t which,
+                                                       uint8_t *term_ranks, int32_t *rank_sums)
+{
+    __shared__ int32_t scratch[64 * 64];
+    const int64_t walk = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (walk >= n_walks) return;
+    const tsf_walk_header *h = hdr + walk;
+    const int m = h->m, n = h->n, p = h->p;
+    const int rank = which == 0 ? h->rank : which == 1 ? h->best_rank : h->start_rank;
+    const bool ok = m >= 1 && n >= 1 && p >= 1 && m * n <= 64 && n * p <= 64 && p * m <= 64 &&
+                    (h->mode == 0 || h->mode == 1) && rank >= 0 && rank <= cap;
+    if (!ok) {
+        if (lane < 3) rank_sums[walk * 3 + lane] = -1;
+        return;
+    }
+    const bool z2 = h->mode == 1;
+    int32_t *M = scratch + lane * 64;
+    int s0 = 0, s1 = 0, s2 = 0;
+    const uint64_t *sc = schemes + (size_t)walk * cap * 6;
+    uint8_t *out = term_ranks + (size_t)walk * cap * 3;
+    for (int k = lane; k < rank; k += 64) {
+        const int a = factor_rank(sc[k * 6 + 0], sc[k * 6 + 1], m, n, z2, M);
+        const int b = factor_rank(sc[k * 6 + 2], sc[k * 6 + 3], n, p, z2, M);
+        const int c = factor_rank(sc[k * 6 + 4], sc[k * 6 + 5], p, m, z2, M);
+        out[k * 3 + 0] = (uint8_t)a;
+        out[k * 3 + 1] = (uint8_t)b;
+        out[k * 3 + 2] = (uint8_t)c;
+        s0 += a;
+        s1 += b;
+        s2 += c;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_xor(s0, off);
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
+    }
+    if (lane == 0) {
+        rank_sums[walk * 3 + 0] = s0;
+        rank_sums[walk * 3 + 1] = s1;
+        rank_sums[walk * 3 + 2] = s2;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side: kernel table and launch
 // ---------------------------------------------------------------------------
@@ -738,6 +787,21 @@ tsf_status tsf_features_from_log(const tsf_flip_log *log, int64_t n, uint16_t *X
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        (hipStream_t)hip_stream, log, n, X);
     if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "feature launch failed");
+    return TSF_OK;
+}
+
+tsf_status tsf_invariants_batch(const tsf_walk_batch *b, int32_t which, uint8_t *term_ranks,
+                                int32_t *rank_sums, void *hip_stream)
+{
+    tsf_status st = check_batch(b);
+    if (st) return st;
+    if (which < 0 || which > 2) return tsf_fail(TSF_E_ARG, "which %d not in 0..2", which);
+    if (b->n_walks == 0) return TSF_OK;
+    if (!term_ranks || !rank_sums) return tsf_fail(TSF_E_ARG, "null output");
+    const uint64_t *src = which == 0 ? b->cur : which == 1 ? b->best : b->start;
+    hipLaunchKernelGGL(invariants_kernel, dim3(b->n_walks), dim3(64), 0, (hipStream_t)hip_stream,
+                       b->hdr, src, b->capacity, b->n_walks, which, term_ranks, rank_sums);
+    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "invariants launch failed");
     return TSF_OK;
 }
 

@@ -66,6 +66,11 @@ class LearnWsC(C.Structure):
                 ("choice_cap", C.c_int32), ("reserved", C.c_int32)]
 
 
+class InvariantsC(C.Structure):
+    _fields_ = [("rank_sum", C.c_int32 * 3), ("type_poly", C.c_int32 * 729),
+                ("sym_poly", C.c_int32 * 729)]
+
+
 class Launch(C.Structure):
     _fields_ = [("lanes_per_walk", C.c_int32), ("waves_per_block", C.c_int32),
                 ("strategy", C.c_int32)]
@@ -135,6 +140,9 @@ def lib():
             ("tsf_walk_learned", [C.c_void_p, P(WalkParams), P(WalkBatchC), P(MlpC), P(LearnWsC),
                                   C.c_int64, P(Launch), C.c_void_p]),
             ("tsf_format_slot", [C.c_int32, C.c_int32, C.c_int32]),
+            ("tsf_scheme_invariants", [P(CScheme), C.c_void_p, P(InvariantsC)]),
+            ("tsf_invariants_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
             ("tsf_meta_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_int32, P(WalkBatchC), C.c_void_p]),
         ]:
@@ -246,6 +254,24 @@ def meta_extend(s: Scheme, axis: int, capacity=None) -> Scheme:
     check(lib().tsf_meta_extend(C.byref(s.c()), axis, C.byref(cs)))
     out._take(cs)
     return out
+
+
+def _poly(arr):
+    a = np.ctypeslib.as_array(arr).reshape(9, 9, 9)
+    return {tuple(int(x) for x in idx): int(a[idx]) for idx in zip(*np.nonzero(a))}
+
+
+def scheme_invariants(s: Scheme) -> dict:
+    """Isotropy invariants (Sec. 3.7): per-term factor ranks, the type and
+    symmetric polynomials ({(a, b, c): coefficient}) and the rank-sum
+    exponents."""
+    out = InvariantsC()
+    ranks = np.zeros((max(s.rank, 1), 3), np.uint8)
+    check(lib().tsf_scheme_invariants(C.byref(s.c()), C.c_void_p(ranks.ctypes.data),
+                                      C.byref(out)))
+    return {"term_ranks": [tuple(int(x) for x in r) for r in ranks[:s.rank]],
+            "type": _poly(out.type_poly), "symmetric": _poly(out.sym_poly),
+            "rank_sum": tuple(int(x) for x in out.rank_sum)}
 
 
 def pack(s: Scheme, capacity=None) -> np.ndarray:
@@ -404,6 +430,18 @@ class WalkBatch:
         la = Launch(lanes_per_walk, waves_per_block, 1)
         check(lib().tsf_walk_learned(ctx.ptr, C.byref(prm), C.byref(self.c()), C.byref(net.c()),
                                      C.byref(ws.c()), int(n_iters), C.byref(la), self._stream()))
+
+    def invariants(self, which=1):
+        """Factor ranks of every live term (uint8, n_walks x capacity x 3; zero
+        past a scheme's rank) and their sums (int32, n_walks x 3) of the cur (0),
+        best (1) or start (2) scheme of every walk, on the GPU."""
+        torch = self.torch
+        ranks = torch.zeros((self.n_walks, self.capacity, 3), dtype=torch.uint8,
+                            device=self.hdr.device)
+        sums = torch.empty((self.n_walks, 3), dtype=torch.int32, device=self.hdr.device)
+        check(lib().tsf_invariants_batch(C.byref(self.c()), which, C.c_void_p(ranks.data_ptr()),
+                                         C.c_void_p(sums.data_ptr()), self._stream()))
+        return ranks, sums
 
     def verify_device(self, which=1):
         """Brent check of cur (0), best (1) or start (2) of every walk on the GPU."""

@@ -236,3 +236,25 @@ def test_meta_on_strassen(lib):
     assert e.rank == 7 + 4 and (e.m, e.n, e.p) == (2, 2, 3) and tsf.verify(e) == 0
     back = tsf.meta_project(e, 2, 2)
     assert sorted(_rows(back)) == sorted(_rows(s))
+
+
+@pytest.mark.parametrize("fmt,target,z2", [((2, 2, 3), 11, False), ((3, 3, 3), 25, False),
+                                           ((2, 3, 4), 22, False), ((2, 2, 3), 11, True)])
+def test_scheme_invariants_match_oracle(lib, fmt, target, z2):
+    """tsf_scheme_invariants (host, the same rank routine as the GPU kernel)
+    against the exact oracle on schemes found by oracle walks."""
+    from oracle import invariants as I
+    m, n, p = fmt
+    prm = O.make_params(seed=3, max_iters=60000, plateau=20000, target_rank=target,
+                        r0=m * n * p, t_expand=1 << 29)
+    ws = O.run_many(O.standard(m, n, p, z2=z2), prm, 3, 0, 6, 60000, 6)
+    for w in ws:
+        for sch in (w.best, w.cur):
+            d = O.from_c(sch)
+            got = tsf.scheme_invariants(_from_oracle(sch, tsf.TSF_Z2 if z2 else tsf.TSF_TERNARY))
+            rk = I.term_ranks(d, m, n, p, z2=z2)
+            assert got["term_ranks"] == rk
+            assert got["type"] == I.type_polynomial(rk)
+            assert got["symmetric"] == I.symmetric_polynomial(rk)
+            sums = tuple(sum(t[k] for t in rk) for k in range(3))
+            assert got["rank_sum"] == sums
