@@ -549,6 +549,166 @@ int or_extend(const or_scheme *in, int axis, or_scheme *out)
     return 0;
 }
 
+/* Swap sizes (Sec. 3.3.2): (m,n,p:r) -> (m,p,n:r).  C^T = B^T A^T turns a
+ * scheme for (m,n,p) into one for (p,n,m) (u' = v^T, v' = u^T, w' = w^T as
+ * matrices), and rotating the factors (u,v,w) -> (v,w,u) turns a scheme for
+ * (m,n,p) into one for (n,p,m) (the C^T layout makes the Brent equations
+ * cyclic); the transpose followed by two rotations gives (m,p,n) with
+ * u'' = w^T (m x p), v'' = v^T (p x n), w'' = u^T (n x m).  Terms renormalised. */
+int or_swap_sizes(const or_scheme *in, or_scheme *out)
+{
+    int m = in->m, n = in->n, p = in->p;
+    memset(out, 0, sizeof(*out));
+    out->m = m; out->n = p; out->p = n; out->z2 = in->z2; out->r = in->r;
+    for (int l = 0; l < in->r; ++l) {
+        for (int k = 0; k < p; ++k)          /* w: p x m, entry (k, i) */
+            for (int i = 0; i < m; ++i) out->f[OR_U][l][i * p + k] = in->f[OR_W][l][k * m + i];
+        for (int j = 0; j < n; ++j)          /* v: n x p, entry (j, k) */
+            for (int k = 0; k < p; ++k) out->f[OR_V][l][k * n + j] = in->f[OR_V][l][j * p + k];
+        for (int i = 0; i < m; ++i)          /* u: m x n, entry (i, j) */
+            for (int j = 0; j < n; ++j) out->f[OR_W][l][j * m + i] = in->f[OR_U][l][i * n + j];
+        or_normalise_term(out, l);
+    }
+    return 0;
+}
+
+/* Merge (Sec. 3.3.2) of (m,n,p1:r1) and (m,n,p2:r2) into (m,n,p1+p2:r1+r2)
+ * (axis 2: C = A [B1 B2], the second scheme's b and c columns shifted by
+ * p1); axis 0: (m1+m2,n,p) from [A1; A2] B; axis 1: (m,n1+n2,p) from
+ * [A1 A2][B1; B2] = A1 B1 + A2 B2.  The terms of a come first.  Returns -1
+ * when the other two dimensions differ or a factor would exceed 64 entries
+ * or the rank OR_MAXT. */
+int or_merge(const or_scheme *a, const or_scheme *b, int axis, or_scheme *out)
+{
+    if (axis < 0 || axis > 2 || a->z2 != b->z2) return -1;
+    if (axis == 0 && (a->n != b->n || a->p != b->p)) return -1;
+    if (axis == 1 && (a->m != b->m || a->p != b->p)) return -1;
+    if (axis == 2 && (a->m != b->m || a->n != b->n)) return -1;
+    int M = axis == 0 ? a->m + b->m : a->m, N = axis == 1 ? a->n + b->n : a->n,
+        P = axis == 2 ? a->p + b->p : a->p;
+    if (M * N > OR_MAXL || N * P > OR_MAXL || P * M > OR_MAXL || a->r + b->r > OR_MAXT) return -1;
+    memset(out, 0, sizeof(*out));
+    out->m = M; out->n = N; out->p = P; out->z2 = a->z2; out->r = a->r + b->r;
+    for (int q = 0; q < 2; ++q) {
+        const or_scheme *s = q ? b : a;
+        int oi = (q && axis == 0) ? a->m : 0, oj = (q && axis == 1) ? a->n : 0,
+            ok = (q && axis == 2) ? a->p : 0;
+        for (int l = 0; l < s->r; ++l) {
+            int L = (q ? a->r : 0) + l;
+            for (int i = 0; i < s->m; ++i)
+                for (int j = 0; j < s->n; ++j)
+                    out->f[OR_U][L][(i + oi) * N + j + oj] = s->f[OR_U][l][i * s->n + j];
+            for (int j = 0; j < s->n; ++j)
+                for (int k = 0; k < s->p; ++k)
+                    out->f[OR_V][L][(j + oj) * P + k + ok] = s->f[OR_V][l][j * s->p + k];
+            for (int k = 0; k < s->p; ++k)
+                for (int i = 0; i < s->m; ++i)
+                    out->f[OR_W][L][(k + ok) * M + i + oi] = s->f[OR_W][l][k * s->m + i];
+        }
+    }
+    for (int l = 0; l < out->r; ++l) or_normalise_term(out, l);
+    return 0;
+}
+
+/* Product (Sec. 3.3.2): the tensor (Kronecker) product of (m1,n1,p1:r1) and
+ * (m2,n2,p2:r2) is a scheme for (m1 m2, n1 n2, p1 p2 : r1 r2): term
+ * l1*r2 + l2 has u = u1 (x) u2 with row i1*m2+i2, column j1*n2+j2 (likewise v,
+ * w).  Returns -1 when a factor would exceed 64 entries or the rank OR_MAXT. */
+int or_product(const or_scheme *a, const or_scheme *b, or_scheme *out)
+{
+    if (a->z2 != b->z2) return -1;
+    int M = a->m * b->m, N = a->n * b->n, P = a->p * b->p;
+    if (M * N > OR_MAXL || N * P > OR_MAXL || P * M > OR_MAXL || a->r * b->r > OR_MAXT) return -1;
+    memset(out, 0, sizeof(*out));
+    out->m = M; out->n = N; out->p = P; out->z2 = a->z2; out->r = a->r * b->r;
+    for (int l1 = 0; l1 < a->r; ++l1)
+        for (int l2 = 0; l2 < b->r; ++l2) {
+            int L = l1 * b->r + l2;
+            for (int i1 = 0; i1 < a->m; ++i1) for (int j1 = 0; j1 < a->n; ++j1)
+                for (int i2 = 0; i2 < b->m; ++i2) for (int j2 = 0; j2 < b->n; ++j2)
+                    out->f[OR_U][L][(i1 * b->m + i2) * N + j1 * b->n + j2] = (int8_t)(
+                        a->f[OR_U][l1][i1 * a->n + j1] * b->f[OR_U][l2][i2 * b->n + j2]);
+            for (int j1 = 0; j1 < a->n; ++j1) for (int k1 = 0; k1 < a->p; ++k1)
+                for (int j2 = 0; j2 < b->n; ++j2) for (int k2 = 0; k2 < b->p; ++k2)
+                    out->f[OR_V][L][(j1 * b->n + j2) * P + k1 * b->p + k2] = (int8_t)(
+                        a->f[OR_V][l1][j1 * a->p + k1] * b->f[OR_V][l2][j2 * b->p + k2]);
+            for (int k1 = 0; k1 < a->p; ++k1) for (int i1 = 0; i1 < a->m; ++i1)
+                for (int k2 = 0; k2 < b->p; ++k2) for (int i2 = 0; i2 < b->m; ++i2)
+                    out->f[OR_W][L][(k1 * b->p + k2) * M + i1 * b->m + i2] = (int8_t)(
+                        a->f[OR_W][l1][k1 * a->m + i1] * b->f[OR_W][l2][k2 * b->m + i2]);
+            or_normalise_term(out, L);
+        }
+    return 0;
+}
+
+/* Resize (Algorithm 2, Sec. 3.4.3) of one scheme s of a walk, given the
+ * population's best schemes.  Reading of the random choices (the paper gives
+ * the probabilities only): Philox blocks b0 = (round, 0, 3) and
+ * b1 = (round, 1, 3) keyed by the walk seed.
+ *   b0.w0 < 2^31: swap sizes.
+ *   merge partner best[U(b0.w1, n_best)]; try the axes p, m, n in that order
+ *   and keep the first merge that exists and fits (rank <= cap).
+ *   No merge and b0.w2 < t_resize: q = b0.w3 picks project (q < 0.05 * 2^32),
+ *   product with best[U(b1.w0, n_best)] (q < 0.55 * 2^32), double (merge
+ *   with itself, q < 0.85 * 2^32) or extend; axis U(b1.w1, 3), project index
+ *   U(b1.w2, dim).  An operator that does not exist or fit leaves the
+ *   scheme unchanged.  Returns the operators applied: bit 0 swap, 1 merge,
+ *   2 project, 3 product, 4 double, 5 extend. */
+#define OR_T_PROJECT 214748365u   /* round(0.05 * 2^32) */
+#define OR_T_PRODUCT 2362232013u  /* round(0.55 * 2^32) */
+#define OR_T_DOUBLE 3650722202u   /* round(0.85 * 2^32) */
+int or_resize(const or_scheme *s, const or_scheme *best, int n_best, uint64_t seed,
+              int64_t round, uint64_t t_resize, int cap, or_scheme *out)
+{
+    or_scheme *tmp = (or_scheme *)malloc(2 * sizeof(or_scheme));  /* ~100 KB each */
+    if (!tmp) return -1;
+    or_scheme *self = tmp + 1;
+    uint32_t b0[4], b1[4];
+    int applied = 0;
+    draw(seed, round, 0, 3, b0);
+    draw(seed, round, 1, 3, b1);
+    *out = *s;
+    if (b0[0] < 0x80000000u) {
+        or_swap_sizes(out, tmp);
+        *out = *tmp;
+        applied |= 1;
+    }
+    if (n_best > 0) {
+        const or_scheme *partner = &best[uniform_below(b0[1], n_best)];
+        static const int order[3] = { 2, 0, 1 };
+        for (int q = 0; q < 3 && !(applied & 2); ++q)
+            if (or_merge(out, partner, order[q], tmp) == 0 && tmp->r <= cap) {
+                *out = *tmp;
+                applied |= 2;
+            }
+    }
+    if (!(applied & 2) && (uint64_t)b0[2] < t_resize) {
+        int axis = uniform_below(b1[1], 3);
+        int dims[3] = { out->m, out->n, out->p };
+        int ok = -1, bit = 0;
+        if (b0[3] < OR_T_PROJECT) {
+            bit = 4;
+            if (dims[axis] >= 2) ok = or_project(out, axis, uniform_below(b1[2], dims[axis]), tmp);
+        } else if (b0[3] < OR_T_PRODUCT) {
+            bit = 8;
+            if (n_best > 0) ok = or_product(out, &best[uniform_below(b1[0], n_best)], tmp);
+        } else if (b0[3] < OR_T_DOUBLE) {
+            bit = 16;
+            *self = *out;
+            ok = or_merge(out, self, axis, tmp);
+        } else {
+            bit = 32;
+            ok = or_extend(out, axis, tmp);
+        }
+        if (ok == 0 && tmp->r <= cap) {
+            *out = *tmp;
+            applied |= bit;
+        }
+    }
+    free(tmp);
+    return applied;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The walk: Algorithm 1 (RandomWalk kernel, Sec. 3.4.2)                     */
 /* ------------------------------------------------------------------------ */

@@ -54,6 +54,11 @@ int  or_is_normalised(const or_scheme *s);
 int  or_project(const or_scheme *in, int axis, int index, or_scheme *out);
 int  or_extend(const or_scheme *in, int axis, or_scheme *out);
 int  or_full_reduce(or_scheme *s);
+int  or_swap_sizes(const or_scheme *in, or_scheme *out);
+int  or_merge(const or_scheme *a, const or_scheme *b, int axis, or_scheme *out);
+int  or_product(const or_scheme *a, const or_scheme *b, or_scheme *out);
+int  or_resize(const or_scheme *s, const or_scheme *best, int n_best, uint64_t seed,
+               int64_t round, uint64_t t_resize, int cap, or_scheme *out);
 
 /* --- the walk (Algorithm 1) ------------------------------------------------ */
 typedef struct {

@@ -67,6 +67,11 @@ def lib():
         L.or_naive_additions.restype = C.c_long
         L.or_nonzeros.argtypes = [P(Scheme)]
         L.or_nonzeros.restype = C.c_long
+        L.or_swap_sizes.argtypes = [P(Scheme), P(Scheme)]
+        L.or_merge.argtypes = [P(Scheme), P(Scheme), C.c_int, P(Scheme)]
+        L.or_product.argtypes = [P(Scheme), P(Scheme), P(Scheme)]
+        L.or_resize.argtypes = [P(Scheme), P(Scheme), C.c_int, C.c_uint64, C.c_int64,
+                                C.c_uint64, C.c_int, P(Scheme)]
         L.or_normalise_term.argtypes = [P(Scheme), C.c_int]
         L.or_is_normalised.argtypes = [P(Scheme)]
         L.or_project.argtypes = [P(Scheme), C.c_int, C.c_int, P(Scheme)]
@@ -149,6 +154,30 @@ def naive_additions(s: Scheme) -> int:
 
 def nonzeros(s: Scheme) -> int:
     return int(lib().or_nonzeros(C.byref(s)))
+
+
+def swap_sizes(s: Scheme) -> Scheme:
+    out = Scheme()
+    lib().or_swap_sizes(C.byref(s), C.byref(out))
+    return out
+
+
+def merge(a: Scheme, b: Scheme, axis: int):
+    out = Scheme()
+    return out if lib().or_merge(C.byref(a), C.byref(b), axis, C.byref(out)) == 0 else None
+
+
+def product(a: Scheme, b: Scheme):
+    out = Scheme()
+    return out if lib().or_product(C.byref(a), C.byref(b), C.byref(out)) == 0 else None
+
+
+def resize(s: Scheme, best, seed: int, rnd: int, t_resize: int, cap: int):
+    """-> (operators applied as bits, new scheme); best: list of Schemes"""
+    arr = (Scheme * max(len(best), 1))(*best) if best else (Scheme * 1)()
+    out = Scheme()
+    bits = lib().or_resize(C.byref(s), arr, len(best), seed, rnd, t_resize, cap, C.byref(out))
+    return bits, out
 
 
 def is_normalised(s: Scheme) -> bool:
