@@ -115,6 +115,26 @@ tsf_status tsf_meta_project(const tsf_scheme *in, int32_t axis, int32_t index, t
  * Errors: TSF_E_ARG, TSF_E_FORMAT (a new length > 64), TSF_E_CAPACITY. */
 tsf_status tsf_meta_extend(const tsf_scheme *in, int32_t axis, tsf_scheme *out);
 
+/* Swap sizes meta operator (Sec. 3.3.2): (m,n,p:r) -> (m,p,n:r).  From
+ * C^T = B^T A^T and the cyclic symmetry of the Brent equations in the C^T
+ * layout: u' = w^T (m x p), v' = v^T (p x n), w' = u^T (n x m); terms
+ * normalised.  out must have capacity >= rank.
+ * Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_NOT_TERNARY, TSF_E_CAPACITY. */
+tsf_status tsf_meta_swap(const tsf_scheme *in, tsf_scheme *out);
+
+/* Merge meta operator (Sec. 3.3.2): along axis 2 (m,n,p1:r1) + (m,n,p2:r2)
+ * -> (m,n,p1+p2:r1+r2), C = A [B1 B2]; along axis 0 [A1; A2] B, along axis 1
+ * [A1 A2][B1; B2].  The terms of a come first, b's indices shifted.
+ * Errors: TSF_E_ARG (modes differ, the other two dimensions differ),
+ * TSF_E_FORMAT (a factor over 64 entries), TSF_E_CAPACITY. */
+tsf_status tsf_meta_merge(const tsf_scheme *a, const tsf_scheme *b, int32_t axis, tsf_scheme *out);
+
+/* Product meta operator (Sec. 3.3.2): the Kronecker product, a scheme for
+ * (m1 m2, n1 n2, p1 p2 : r1 r2); term l1*r2 + l2 = (u1 (x) u2, v1 (x) v2,
+ * w1 (x) w2) with row i1*m2 + i2 and column j1*n2 + j2 in u (likewise v, w).
+ * Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_CAPACITY. */
+tsf_status tsf_meta_product(const tsf_scheme *a, const tsf_scheme *b, tsf_scheme *out);
+
 /* Isotropy invariants (Sec. 3.7).  Each factor of term l is read as a matrix
  * (u: m x n, entry a_ij at row i, column j; v: n x p; w: p x m, entry c_ik at
  * row k, column i) and its rank taken over Q for ternary schemes, over GF(2)
@@ -330,6 +350,50 @@ tsf_status tsf_verify_batch(const tsf_walk_batch *b, int32_t which, int64_t *n_v
  * stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
 tsf_status tsf_invariants_batch(const tsf_walk_batch *b, int32_t which, uint8_t *term_ranks,
                                 int32_t *rank_sums, void *hip_stream);
+
+/* Population synchronisation (Sec. 3.4.1): the distinct formats among the
+ * walks of a batch (walks flagged invalid excluded) and, per format, the walk
+ * with the best rank (ties: the lowest walk id).  table (device, >= slots
+ * entries) receives them in ascending (m, n, p) order, *n_entries (device)
+ * their number.  work (device, 2*slots + 1 uint64) is scratch; slots bounds
+ * the number of distinct formats (more are dropped and counted in the last
+ * word of work).  Async on the stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
+typedef struct {
+    int32_t m, n, p, rank;
+    int64_t walk;
+} tsf_best_entry;
+
+tsf_status tsf_population_best(const tsf_walk_batch *b, tsf_best_entry *table, int32_t *n_entries,
+                               uint64_t *work, int32_t slots, void *hip_stream);
+
+/* Resize (Algorithm 2, Sec. 3.4.3) of every walk, on the GPU: the current
+ * (which = 0) or best (1) scheme of walk w of `in` becomes the start scheme
+ * of walk w of `out` after: with probability 1/2 swap sizes; a merge with a
+ * best scheme of the table (axes p, m, n: the first that exists and fits);
+ * if there was none, with probability t_resize/2^32 one of project (5%),
+ * product with a best scheme (50%), double (30%), extend (15%).  Random words:
+ * Philox4x32-10 blocks (round, 0, 3) and (round, 1, 3) keyed by base_seed +
+ * first_walk_id + w; the exact use of each word is the oracle's or_resize.
+ * An operator whose result would not fit (a factor over 64 entries, rank over
+ * out->capacity) is skipped.  out->hdr[w] receives the format, mode, target,
+ * start_rank and r_cap = min(start_rank + r_cap_extra, out->capacity);
+ * follow with tsf_walk_init(out).  applied (optional, device, n_walks int32):
+ * the operators applied, bit 0 swap, 1 merge, 2 project, 3 product, 4 double,
+ * 5 extend (-1 for a walk that was skipped).  in and out are distinct
+ * batches of equal n_walks; table and *n_entries as from tsf_population_best
+ * on `in`.  Async on the stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
+typedef struct {
+    uint64_t base_seed;
+    int64_t first_walk_id;
+    int64_t round;
+    uint64_t t_resize;         /* p_resize of Alg. 2 as a threshold on 2^32     */
+    int32_t r_cap_extra;
+    int32_t reserved;
+} tsf_resize_params;
+
+tsf_status tsf_resize_batch(const tsf_walk_batch *in, int32_t which, const tsf_best_entry *table,
+                            const int32_t *n_entries, const tsf_resize_params *prm,
+                            const tsf_walk_batch *out, int32_t *applied, void *hip_stream);
 
 /* Meta operators (Sec. 3.3.2) on every walk of a batch at once, on the GPU:
  * the current (which = 0) or best (which = 1) scheme of walk w of `in`

@@ -3,6 +3,7 @@
 // normalisation, reduction and the project/extend meta operators.
 #include "../../include/tsf.h"
 #include "tsf_bits.h"
+#include "tsf_meta.h"
 #include "tsf_internal.h"
 
 #include <cstdarg>
@@ -384,6 +385,101 @@ tsf_status tsf_pack(const tsf_scheme *in, uint64_t *packed)
     if ((st = to_terms(in, t))) return st;
     std::memset(packed, 0, (size_t)in->d.capacity * 6 * sizeof(uint64_t));
     for (size_t l = 0; l < t.size(); ++l) std::memcpy(packed + 6 * l, t[l].f, sizeof(Term));
+    return TSF_OK;
+}
+
+namespace {
+tsf_status check_out(const tsf_scheme *out, int rank)
+{
+    if (!out || !out->U || !out->V || !out->W) return fail(TSF_E_ARG, "null output scheme");
+    if (out->d.capacity < rank)
+        return fail(TSF_E_CAPACITY, "output capacity %d < rank %d", out->d.capacity, rank);
+    return TSF_OK;
+}
+
+void set_out(tsf_scheme *out, int m, int n, int p, int mode, std::vector<Term> &t)
+{
+    out->d.m = m;
+    out->d.n = n;
+    out->d.p = p;
+    out->d.mode = mode;
+    out->d.rank = (int32_t)t.size();
+    from_terms(t, out);
+}
+}  // namespace
+
+tsf_status tsf_meta_swap(const tsf_scheme *in, tsf_scheme *out)
+{
+    if (!in || !in->U || !in->V || !in->W) return fail(TSF_E_ARG, "null scheme");
+    tsf_status st = check_dims(in->d);
+    if (st) return st;
+    std::vector<Term> t;
+    if ((st = to_terms(in, t))) return st;
+    if ((st = check_out(out, (int)t.size()))) return st;
+    const int m = in->d.m, n = in->d.n, p = in->d.p;
+    for (Term &x : t) {
+        uint64_t o[6];
+        term_swap(x.f, m, n, p, o);
+        for (int e = 0; e < 6; ++e) x.f[e] = o[e];
+    }
+    set_out(out, m, p, n, in->d.mode, t);
+    return TSF_OK;
+}
+
+tsf_status tsf_meta_merge(const tsf_scheme *a, const tsf_scheme *b, int32_t axis, tsf_scheme *out)
+{
+    if (!a || !b || !a->U || !b->U) return fail(TSF_E_ARG, "null scheme");
+    tsf_status st = check_dims(a->d);
+    if (st || (st = check_dims(b->d))) return st;
+    if (a->d.mode != b->d.mode) return fail(TSF_E_ARG, "modes differ");
+    if (axis < 0 || axis > 2) return fail(TSF_E_ARG, "axis %d not in 0..2", axis);
+    const int m = a->d.m, n = a->d.n, p = a->d.p;
+    const int bm = b->d.m, bn = b->d.n, bp = b->d.p;
+    if ((axis == 0 && (n != bn || p != bp)) || (axis == 1 && (m != bm || p != bp)) ||
+        (axis == 2 && (m != bm || n != bn)))
+        return fail(TSF_E_ARG, "formats do not merge along axis %d", axis);
+    const int M = axis == 0 ? m + bm : m, N = axis == 1 ? n + bn : n, P = axis == 2 ? p + bp : p;
+    if (M * N > 64 || N * P > 64 || P * M > 64)
+        return fail(TSF_E_FORMAT, "merged factors exceed 64 entries");
+    std::vector<Term> ta, tb;
+    if ((st = to_terms(a, ta)) || (st = to_terms(b, tb))) return st;
+    if ((st = check_out(out, (int)(ta.size() + tb.size())))) return st;
+    std::vector<Term> t;
+    for (const Term &x : ta) {
+        Term y;
+        term_embed(x.f, m, n, p, M, N, P, 0, 0, 0, y.f);
+        t.push_back(y);
+    }
+    for (const Term &x : tb) {
+        Term y;
+        term_embed(x.f, bm, bn, bp, M, N, P, axis == 0 ? m : 0, axis == 1 ? n : 0, axis == 2 ? p : 0,
+                   y.f);
+        t.push_back(y);
+    }
+    set_out(out, M, N, P, a->d.mode, t);
+    return TSF_OK;
+}
+
+tsf_status tsf_meta_product(const tsf_scheme *a, const tsf_scheme *b, tsf_scheme *out)
+{
+    if (!a || !b || !a->U || !b->U) return fail(TSF_E_ARG, "null scheme");
+    tsf_status st = check_dims(a->d);
+    if (st || (st = check_dims(b->d))) return st;
+    if (a->d.mode != b->d.mode) return fail(TSF_E_ARG, "modes differ");
+    const int M = a->d.m * b->d.m, N = a->d.n * b->d.n, P = a->d.p * b->d.p;
+    if (M * N > 64 || N * P > 64 || P * M > 64)
+        return fail(TSF_E_FORMAT, "product factors exceed 64 entries");
+    std::vector<Term> ta, tb;
+    if ((st = to_terms(a, ta)) || (st = to_terms(b, tb))) return st;
+    if ((st = check_out(out, (int)(ta.size() * tb.size())))) return st;
+    std::vector<Term> t;
+    for (const Term &x : ta)
+        for (const Term &y : tb) {
+            Term z;
+            term_kron(x.f, a->d.m, a->d.n, a->d.p, y.f, b->d.m, b->d.n, b->d.p, z.f);
+            t.push_back(z);
+        }
+    set_out(out, M, N, P, a->d.mode, t);
     return TSF_OK;
 }
 

@@ -3,6 +3,7 @@
 // (walk_kernel.h, instantiated in walk_inst.hip).
 #include "walk_kernel.h"
 #include "tsf_internal.h"
+#include "tsf_meta.h"
 
 #include <cstring>
 #include <vector>
@@ -297,6 +298,284 @@ __global__ void __launch_bounds__(64) invariants_kernel(const tsf_walk_header *h
         rank_sums[walk * 3 + 0] = s0;
         rank_sums[walk * 3 + 1] = s1;
         rank_sums[walk * 3 + 2] = s2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Population synchronisation and the Resize kernel (Sec. 3.4.1, Algorithm 2)
+// ---------------------------------------------------------------------------
+__global__ void clear_table_kernel(unsigned long long *keys, unsigned long long *vals, int slots,
+                                   int32_t *overflow)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < slots) {
+        keys[q] = 0;
+        vals[q] = ~0ull;
+    }
+    if (q == 0) *overflow = 0;
+}
+
+// One thread per walk: insert the walk's format into an open-addressing
+// table (key = 1 | m << 8 | n << 16 | p << 24) and keep, per format, the
+// smallest (best rank << 32 | walk id).
+__global__ void best_insert_kernel(const tsf_walk_header *hdr, int32_t n_walks,
+                                   unsigned long long *keys, unsigned long long *vals, int slots,
+                                   int32_t *overflow)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_walks) return;
+    const tsf_walk_header *h = hdr + w;
+    if (h->done < 0 || h->m < 1 || h->m > 64 || h->n < 1 || h->n > 64 || h->p < 1 || h->p > 64)
+        return;
+    const unsigned long long key = 1ull | ((unsigned long long)h->m << 8) |
+                                   ((unsigned long long)h->n << 16) | ((unsigned long long)h->p << 24);
+    const unsigned long long val = ((unsigned long long)(uint32_t)h->best_rank << 32) | (uint64_t)w;
+    int q = (int)((key * 0x9E3779B97F4A7C15ull) >> 40) % slots;
+    for (int probe = 0; probe < slots; ++probe) {
+        const unsigned long long prev = atomicCAS(&keys[q], 0ull, key);
+        if (prev == 0 || prev == key) {
+            atomicMin(&vals[q], val);
+            return;
+        }
+        q = q + 1 == slots ? 0 : q + 1;
+    }
+    atomicAdd(overflow, 1);
+}
+
+// One workgroup: the occupied slots in ascending (m, n, p) order -> table.
+__global__ void __launch_bounds__(256) best_compact_kernel(const unsigned long long *keys,
+                                                           const unsigned long long *vals,
+                                                           int slots, tsf_best_entry *table,
+                                                           int32_t *n_entries)
+{
+    for (int q = threadIdx.x; q < slots; q += blockDim.x) {
+        const unsigned long long k = keys[q];
+        if (!k) continue;
+        const unsigned long long ord = ((k >> 8) & 0xFF) << 16 | ((k >> 16) & 0xFF) << 8 |
+                                       ((k >> 24) & 0xFF);
+        int pos = 0;
+        for (int x = 0; x < slots; ++x) {
+            const unsigned long long kx = keys[x];
+            if (!kx) continue;
+            const unsigned long long ox = ((kx >> 8) & 0xFF) << 16 | ((kx >> 16) & 0xFF) << 8 |
+                                          ((kx >> 24) & 0xFF);
+            pos += ox < ord;
+        }
+        tsf_best_entry e;
+        e.m = (int32_t)((k >> 8) & 0xFF);
+        e.n = (int32_t)((k >> 16) & 0xFF);
+        e.p = (int32_t)((k >> 24) & 0xFF);
+        e.rank = (int32_t)(vals[q] >> 32);
+        e.walk = (int64_t)(vals[q] & 0xFFFFFFFFull);
+        table[pos] = e;
+    }
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int x = 0; x < slots; ++x) c += keys[x] != 0;
+        *n_entries = c;
+    }
+}
+
+// Algorithm 2 on every walk (one wavefront per walk): the walk's current or
+// best scheme, after the operators drawn from Philox blocks (round, 0, 3)
+// and (round, 1, 3) of its seed, becomes its start scheme in `out` (the
+// oracle's or_resize states the same reading).  Partners are the best
+// schemes of the table, read from in.best.  Lanes handle output terms.
+__global__ void __launch_bounds__(64) resize_kernel(tsf_walk_batch in, int32_t which,
+                                                    const tsf_best_entry *table,
+                                                    const int32_t *n_entries, uint64_t base_seed,
+                                                    int64_t first_walk_id, int64_t round,
+                                                    uint64_t t_resize, int32_t r_cap_extra,
+                                                    tsf_walk_batch out, int32_t *applied_out)
+{
+    const int64_t walk = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (walk >= in.n_walks) return;
+    const tsf_walk_header *h = in.hdr + walk;
+    tsf_walk_header *ho = out.hdr + walk;
+    const int m0 = h->m, n0 = h->n, p0 = h->p;
+    const int r0 = which ? h->best_rank : h->rank;
+    const int nb = *n_entries;
+    const bool sane = h->done >= 0 && m0 >= 1 && n0 >= 1 && p0 >= 1 && m0 * n0 <= 64 &&
+                      n0 * p0 <= 64 && p0 * m0 <= 64 && r0 >= 1 && r0 <= in.capacity &&
+                      r0 <= out.capacity;
+    const uint64_t seed = base_seed + (uint64_t)(first_walk_id + walk);
+    const Philox4 b0 = walk_block(seed, round, 0, 3), b1 = walk_block(seed, round, 1, 3);
+    const uint64_t *src = (which ? in.best : in.cur) + (size_t)walk * in.capacity * 6;
+    uint64_t *dst = const_cast<uint64_t *>(out.start) + (size_t)walk * out.capacity * 6;
+    const bool swp = sane && b0.x[0] < 0x80000000u;
+    // format after the optional swap
+    const int m = m0, n = swp ? p0 : n0, p = swp ? n0 : p0;
+    auto term = [&](int k, uint64_t (&f)[6]) {
+        uint64_t g[6];
+        for (int x = 0; x < 6; ++x) g[x] = src[k * 6 + x];
+        if (swp)
+            term_swap(g, m0, n0, p0, f);
+        else
+            for (int x = 0; x < 6; ++x) f[x] = g[x];
+    };
+    int applied = swp ? 1 : 0;
+    int op = 0;  // 0 keep, 2 merge, 4 project, 8 product, 16 double, 32 extend
+    int axis = 0, pidx = 0, M = m, N = n, P = p, R = r0;
+    int64_t partner = -1;
+    int pm = 0, pn = 0, pp = 0, pr = 0;
+    if (sane && nb > 0) {
+        const tsf_best_entry e = table[below(b0.x[1], (uint32_t)nb)];
+        const int order[3] = {2, 0, 1};
+        for (int q = 0; q < 3 && op == 0; ++q) {
+            const int ax = order[q];
+            const bool compat = ax == 2 ? (e.m == m && e.n == n) : ax == 0 ? (e.n == n && e.p == p)
+                                                                            : (e.m == m && e.p == p);
+            const int M2 = ax == 0 ? m + e.m : m, N2 = ax == 1 ? n + e.n : n,
+                      P2 = ax == 2 ? p + e.p : p;
+            if (compat && M2 * N2 <= 64 && N2 * P2 <= 64 && P2 * M2 <= 64 &&
+                r0 + e.rank <= out.capacity) {
+                op = 2;
+                axis = ax;
+                M = M2; N = N2; P = P2; R = r0 + e.rank;
+                partner = e.walk;
+                pm = e.m; pn = e.n; pp = e.p; pr = e.rank;
+            }
+        }
+    }
+    if (sane && op == 0 && (uint64_t)b0.x[2] < t_resize) {
+        axis = (int)below(b1.x[1], 3u);
+        const int dim = axis == 0 ? m : axis == 1 ? n : p;
+        const uint32_t q = b0.x[3];
+        if (q < 214748365u) {  // round(0.05 * 2^32): project
+            if (dim >= 2) {
+                op = 4;
+                pidx = (int)below(b1.x[2], (uint32_t)dim);
+                M = m - (axis == 0); N = n - (axis == 1); P = p - (axis == 2);
+            }
+        } else if (q < 2362232013u) {  // round(0.55 * 2^32): product
+            if (nb > 0) {
+                const tsf_best_entry e = table[below(b1.x[0], (uint32_t)nb)];
+                const int M2 = m * e.m, N2 = n * e.n, P2 = p * e.p;
+                if (M2 * N2 <= 64 && N2 * P2 <= 64 && P2 * M2 <= 64 &&
+                    (int64_t)r0 * e.rank <= out.capacity) {
+                    op = 8;
+                    M = M2; N = N2; P = P2; R = r0 * e.rank;
+                    partner = e.walk;
+                    pm = e.m; pn = e.n; pp = e.p; pr = e.rank;
+                }
+            }
+        } else if (q < 3650722202u) {  // round(0.85 * 2^32): double
+            const int M2 = axis == 0 ? 2 * m : m, N2 = axis == 1 ? 2 * n : n,
+                      P2 = axis == 2 ? 2 * p : p;
+            if (M2 * N2 <= 64 && N2 * P2 <= 64 && P2 * M2 <= 64 && 2 * r0 <= out.capacity) {
+                op = 16;
+                M = M2; N = N2; P = P2; R = 2 * r0;
+            }
+        } else {  // extend
+            const int M2 = m + (axis == 0), N2 = n + (axis == 1), P2 = p + (axis == 2);
+            const int extra = axis == 0 ? n * p : axis == 1 ? m * p : m * n;
+            if (M2 * N2 <= 64 && N2 * P2 <= 64 && P2 * M2 <= 64 && r0 + extra <= out.capacity) {
+                op = 32;
+                M = M2; N = N2; P = P2; R = r0 + extra;
+            }
+        }
+    }
+    applied |= op;
+    const uint64_t *psrc = partner >= 0 ? in.best + (size_t)partner * in.capacity * 6 : nullptr;
+    int count = 0;
+    if (sane) {
+        if (op == 0 || op == 2 || op == 16 || op == 32) {
+            // the walk's own terms, embedded (offset 0)
+            for (int k = lane; k < r0; k += 64) {
+                uint64_t f[6], o[6];
+                term(k, f);
+                term_embed(f, m, n, p, M, N, P, 0, 0, 0, o);
+                for (int x = 0; x < 6; ++x) dst[k * 6 + x] = o[x];
+            }
+            count = r0;
+        }
+        if (op == 2) {
+            const int oi = axis == 0 ? m : 0, oj = axis == 1 ? n : 0, ok = axis == 2 ? p : 0;
+            for (int k = lane; k < pr; k += 64) {
+                uint64_t f[6], o[6];
+                for (int x = 0; x < 6; ++x) f[x] = psrc[k * 6 + x];
+                term_embed(f, pm, pn, pp, M, N, P, oi, oj, ok, o);
+                for (int x = 0; x < 6; ++x) dst[(r0 + k) * 6 + x] = o[x];
+            }
+            count = R;
+        } else if (op == 16) {
+            const int oi = axis == 0 ? m : 0, oj = axis == 1 ? n : 0, ok = axis == 2 ? p : 0;
+            for (int k = lane; k < r0; k += 64) {
+                uint64_t f[6], o[6];
+                term(k, f);
+                term_embed(f, m, n, p, M, N, P, oi, oj, ok, o);
+                for (int x = 0; x < 6; ++x) dst[(r0 + k) * 6 + x] = o[x];
+            }
+            count = R;
+        } else if (op == 32) {
+            const int extra = R - r0;
+            for (int q = lane; q < extra; q += 64) {
+                int i, j, k;
+                if (axis == 2) { i = q / n; j = q % n; k = p; }
+                else if (axis == 0) { i = m; j = q / p; k = q % p; }
+                else { i = q / p; j = n; k = q % p; }
+                uint64_t *d = dst + (size_t)(r0 + q) * 6;
+                d[0] = 1ull << (i * N + j);
+                d[1] = 0;
+                d[2] = 1ull << (j * P + k);
+                d[3] = 0;
+                d[4] = 1ull << (k * M + i);
+                d[5] = 0;
+            }
+            count = R;
+        } else if (op == 8) {
+            for (int q = lane; q < R; q += 64) {
+                const int l1 = q / pr, l2 = q % pr;
+                uint64_t f[6], g[6], o[6];
+                term(l1, f);
+                for (int x = 0; x < 6; ++x) g[x] = psrc[l2 * 6 + x];
+                term_kron(f, m, n, p, g, pm, pn, pp, o);
+                for (int x = 0; x < 6; ++x) dst[q * 6 + x] = o[x];
+            }
+            count = R;
+        } else if (op == 4) {
+            // project: drop index pidx of `axis`, keep the non-zero terms in order
+            const int cu = n, cv = p, cw = m;
+            const int dr_u = axis == 0 ? pidx : -1, dc_u = axis == 1 ? pidx : -1;
+            const int dr_v = axis == 1 ? pidx : -1, dc_v = axis == 2 ? pidx : -1;
+            const int dr_w = axis == 2 ? pidx : -1, dc_w = axis == 0 ? pidx : -1;
+            for (int base = 0; base < r0; base += 64) {
+                const int k = base + lane;
+                uint64_t f[6], o[6] = {0, 0, 0, 0, 0, 0};
+                bool keep = false;
+                if (k < r0) {
+                    term(k, f);
+                    o[0] = remap_mask(f[0], cu, N, dr_u, dc_u);
+                    o[1] = remap_mask(f[1], cu, N, dr_u, dc_u);
+                    o[2] = remap_mask(f[2], cv, P, dr_v, dc_v);
+                    o[3] = remap_mask(f[3], cv, P, dr_v, dc_v);
+                    o[4] = remap_mask(f[4], cw, M, dr_w, dc_w);
+                    o[5] = remap_mask(f[5], cw, M, dr_w, dc_w);
+                    keep = o[0] != 0 && o[2] != 0 && o[4] != 0;
+                    normalise_packed(o);
+                }
+                const uint64_t mk = __ballot(keep);
+                const int pos = count + __builtin_amdgcn_mbcnt_hi(
+                                            (uint32_t)(mk >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
+                if (keep)
+                    for (int x = 0; x < 6; ++x) dst[pos * 6 + x] = o[x];
+                count += __builtin_popcountll(mk);
+            }
+            R = count;
+        }
+    }
+    if (lane == 0) {
+        ho->m = sane ? M : m0;
+        ho->n = sane ? N : n0;
+        ho->p = sane ? P : p0;
+        ho->mode = h->mode;
+        ho->target_rank = h->target_rank;
+        ho->start_rank = sane ? count : -1;
+        const int rc = count + r_cap_extra;
+        ho->r_cap = rc < out.capacity ? rc : out.capacity;
+        if (applied_out) applied_out[walk] = sane ? applied : -1;
     }
 }
 
@@ -787,6 +1066,51 @@ tsf_status tsf_features_from_log(const tsf_flip_log *log, int64_t n, uint16_t *X
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        (hipStream_t)hip_stream, log, n, X);
     if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "feature launch failed");
+    return TSF_OK;
+}
+
+tsf_status tsf_population_best(const tsf_walk_batch *b, tsf_best_entry *table, int32_t *n_entries,
+                               uint64_t *work, int32_t slots, void *hip_stream)
+{
+    tsf_status st = check_batch(b);
+    if (st) return st;
+    if (slots < 1 || slots > 65536) return tsf_fail(TSF_E_ARG, "slots %d outside [1, 65536]", slots);
+    if (!table || !n_entries || !work) return tsf_fail(TSF_E_ARG, "null table or workspace");
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned long long *keys = (unsigned long long *)work, *vals = keys + slots;
+    int32_t *overflow = (int32_t *)(vals + slots);
+    hipLaunchKernelGGL(clear_table_kernel, dim3((slots + 255) / 256), dim3(256), 0, s, keys, vals,
+                       slots, overflow);
+    if (b->n_walks > 0)
+        hipLaunchKernelGGL(best_insert_kernel, dim3((b->n_walks + 255) / 256), dim3(256), 0, s,
+                           b->hdr, b->n_walks, keys, vals, slots, overflow);
+    hipLaunchKernelGGL(best_compact_kernel, dim3(1), dim3(256), 0, s, keys, vals, slots, table,
+                       n_entries);
+    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "population launch failed");
+    return TSF_OK;
+}
+
+tsf_status tsf_resize_batch(const tsf_walk_batch *in, int32_t which, const tsf_best_entry *table,
+                            const int32_t *n_entries, const tsf_resize_params *prm,
+                            const tsf_walk_batch *out, int32_t *applied, void *hip_stream)
+{
+    tsf_status st = check_batch(in);
+    if (st) return st;
+    if ((st = check_batch(out))) return st;
+    if (in->n_walks != out->n_walks) return tsf_fail(TSF_E_ARG, "batches differ in n_walks");
+    if (which < 0 || which > 1) return tsf_fail(TSF_E_ARG, "which %d not in 0..1", which);
+    if (!prm || !table || !n_entries) return tsf_fail(TSF_E_ARG, "null argument");
+    if (prm->r_cap_extra < 0 || prm->t_resize > (1ull << 32))
+        return tsf_fail(TSF_E_ARG, "bad resize parameters");
+    if (in->mode != out->mode) return tsf_fail(TSF_E_ARG, "batches differ in mode");
+    if ((const void *)in->start == (const void *)out->start || in->cur == out->start ||
+        in->best == out->start)
+        return tsf_fail(TSF_E_ARG, "in and out must not share scheme buffers");
+    if (in->n_walks == 0) return TSF_OK;
+    hipLaunchKernelGGL(resize_kernel, dim3(in->n_walks), dim3(64), 0, (hipStream_t)hip_stream, *in,
+                       which, table, n_entries, prm->base_seed, prm->first_walk_id, prm->round,
+                       prm->t_resize, prm->r_cap_extra, *out, applied);
+    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "resize launch failed");
     return TSF_OK;
 }
 

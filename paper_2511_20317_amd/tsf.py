@@ -71,6 +71,15 @@ class InvariantsC(C.Structure):
                 ("sym_poly", C.c_int32 * 729)]
 
 
+class ResizeParams(C.Structure):
+    _fields_ = [("base_seed", C.c_uint64), ("first_walk_id", C.c_int64), ("round", C.c_int64),
+                ("t_resize", C.c_uint64), ("r_cap_extra", C.c_int32), ("reserved", C.c_int32)]
+
+
+BEST_ENTRY_DTYPE = np.dtype([("m", "<i4"), ("n", "<i4"), ("p", "<i4"), ("rank", "<i4"),
+                             ("walk", "<i8")])
+
+
 class Launch(C.Structure):
     _fields_ = [("lanes_per_walk", C.c_int32), ("waves_per_block", C.c_int32),
                 ("strategy", C.c_int32)]
@@ -141,6 +150,13 @@ def lib():
                                   C.c_int64, P(Launch), C.c_void_p]),
             ("tsf_format_slot", [C.c_int32, C.c_int32, C.c_int32]),
             ("tsf_scheme_invariants", [P(CScheme), C.c_void_p, P(InvariantsC)]),
+            ("tsf_meta_swap", [P(CScheme), P(CScheme)]),
+            ("tsf_meta_merge", [P(CScheme), P(CScheme), C.c_int32, P(CScheme)]),
+            ("tsf_meta_product", [P(CScheme), P(CScheme), P(CScheme)]),
+            ("tsf_population_best", [P(WalkBatchC), C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_int32, C.c_void_p]),
+            ("tsf_resize_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p,
+                                  P(ResizeParams), P(WalkBatchC), C.c_void_p, C.c_void_p]),
             ("tsf_invariants_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
             ("tsf_meta_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -252,6 +268,35 @@ def meta_extend(s: Scheme, axis: int, capacity=None) -> Scheme:
     out = Scheme.empty(*dims, capacity or (s.rank + extra), s.mode)
     cs = out.c()
     check(lib().tsf_meta_extend(C.byref(s.c()), axis, C.byref(cs)))
+    out._take(cs)
+    return out
+
+
+def meta_swap(s: Scheme) -> Scheme:
+    """(m,n,p:r) -> (m,p,n:r) (tsf_meta_swap)."""
+    out = Scheme.empty(s.m, s.p, s.n, max(s.rank, 1), s.mode)
+    cs = out.c()
+    check(lib().tsf_meta_swap(C.byref(s.c()), C.byref(cs)))
+    out._take(cs)
+    return out
+
+
+def meta_merge(a: Scheme, b: Scheme, axis: int) -> Scheme:
+    """Merge along axis 0 (m), 1 (n) or 2 (p) (tsf_meta_merge)."""
+    dims = [a.m, a.n, a.p]
+    dims[axis] += [b.m, b.n, b.p][axis]
+    out = Scheme.empty(*dims, max(a.rank + b.rank, 1), a.mode)
+    cs = out.c()
+    check(lib().tsf_meta_merge(C.byref(a.c()), C.byref(b.c()), axis, C.byref(cs)))
+    out._take(cs)
+    return out
+
+
+def meta_product(a: Scheme, b: Scheme) -> Scheme:
+    """Kronecker product of two schemes (tsf_meta_product)."""
+    out = Scheme.empty(a.m * b.m, a.n * b.n, a.p * b.p, max(a.rank * b.rank, 1), a.mode)
+    cs = out.c()
+    check(lib().tsf_meta_product(C.byref(a.c()), C.byref(b.c()), C.byref(cs)))
     out._take(cs)
     return out
 
@@ -442,6 +487,33 @@ class WalkBatch:
         check(lib().tsf_invariants_batch(C.byref(self.c()), which, C.c_void_p(ranks.data_ptr()),
                                          C.c_void_p(sums.data_ptr()), self._stream()))
         return ranks, sums
+
+    def population_best(self, slots=256):
+        """Per distinct format, the walk with the best rank (ties: lowest id),
+        ascending (m, n, p): (device table of BEST_ENTRY_DTYPE records as a
+        uint8 tensor, device int32 count) -- tsf_population_best."""
+        torch = self.torch
+        dev = self.hdr.device
+        table = torch.zeros(slots * BEST_ENTRY_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        count = torch.zeros(1, dtype=torch.int32, device=dev)
+        work = torch.empty(2 * slots + 1, dtype=torch.int64, device=dev)
+        check(lib().tsf_population_best(C.byref(self.c()), C.c_void_p(table.data_ptr()),
+                                        C.c_void_p(count.data_ptr()),
+                                        C.c_void_p(work.data_ptr()), slots, self._stream()))
+        return table, count
+
+    def resize_into(self, out, table, count, base_seed, rnd, t_resize=ALWAYS, which=1,
+                    r_cap_extra=8, first_walk_id=0):
+        """Algorithm 2 on every walk into batch `out` (tsf_resize_batch); then
+        out.init.  Returns the device tensor of operator bits per walk."""
+        torch = self.torch
+        applied = torch.empty(self.n_walks, dtype=torch.int32, device=self.hdr.device)
+        prm = ResizeParams(base_seed, first_walk_id, rnd, t_resize, r_cap_extra, 0)
+        check(lib().tsf_resize_batch(C.byref(self.c()), which, C.c_void_p(table.data_ptr()),
+                                     C.c_void_p(count.data_ptr()), C.byref(prm),
+                                     C.byref(out.c()), C.c_void_p(applied.data_ptr()),
+                                     self._stream()))
+        return applied
 
     def verify_device(self, which=1):
         """Brent check of cur (0), best (1) or start (2) of every walk on the GPU."""

@@ -258,3 +258,41 @@ def test_scheme_invariants_match_oracle(lib, fmt, target, z2):
             assert got["symmetric"] == I.symmetric_polynomial(rk)
             sums = tuple(sum(t[k] for t in rk) for k in range(3))
             assert got["rank_sum"] == sums
+
+
+def _walked_oracle(fmt, seed, iters=5000):
+    m, n, p = fmt
+    prm = O.make_params(seed=seed, max_iters=iters, plateau=3000, target_rank=0, r0=m * n * p,
+                        t_expand=1 << 28)
+    w = O.new_walk(O.standard(m, n, p))
+    O.run(w, prm, iters)
+    return O.copy(w.cur)
+
+
+def test_meta_swap_merge_product_match_oracle(lib):
+    """tsf_meta_swap / merge / product (the packed-term routines the resize
+    kernel uses) against the oracle's int8 operators, term by term."""
+    cases = [_walked_oracle((2, 3, 4), 1), _walked_oracle((2, 2, 3), 2), _walked_oracle((3, 3, 2), 3)]
+    for s in cases:
+        want = O.from_c(O.swap_sizes(s))
+        got = tsf.meta_swap(_from_oracle(s))
+        assert (got.m, got.n, got.p) == (s.m, s.p, s.n)
+        assert _rows(got) == [tuple(want["U"][l]) + tuple(want["V"][l]) + tuple(want["W"][l])
+                              for l in range(s.r)]
+    a, b = _walked_oracle((2, 2, 3), 4), _walked_oracle((2, 2, 2), 5)
+    for axis, (x, y) in [(2, (a, b)), (0, (_walked_oracle((1, 2, 3), 6), a)),
+                         (1, (a, _walked_oracle((2, 1, 3), 7)))]:
+        want = O.from_c(O.merge(x, y, axis))
+        got = tsf.meta_merge(_from_oracle(x), _from_oracle(y), axis)
+        assert _rows(got) == [tuple(want["U"][l]) + tuple(want["V"][l]) + tuple(want["W"][l])
+                              for l in range(want["r"])]
+        assert tsf.verify(got) == 0
+    x, y = _walked_oracle((2, 2, 2), 8), _walked_oracle((1, 2, 2), 9)
+    want = O.from_c(O.product(x, y))
+    got = tsf.meta_product(_from_oracle(x), _from_oracle(y))
+    assert (got.m, got.n, got.p, got.rank) == (2, 4, 4, x.r * y.r)
+    assert _rows(got) == [tuple(want["U"][l]) + tuple(want["V"][l]) + tuple(want["W"][l])
+                          for l in range(want["r"])]
+    assert tsf.verify(got) == 0
+    with pytest.raises(tsf.TsfError):
+        tsf.meta_merge(_from_oracle(x), _from_oracle(_walked_oracle((2, 3, 3), 1)), 2)
