@@ -314,6 +314,32 @@ def run_additions(ctx, args):
                            "distinct_type_polynomials": len(types)}}
 
 
+def run_explore(ctx, args):
+    """Exploratory search: a population of args.walks walks starting from the
+    standard schemes of (2,2,2), (2,2,3), (2,3,3), (3,3,3) (a quarter each),
+    capacity 128 terms, rounds of args.iters iterations, each followed by the
+    population synchronisation and the Resize kernel; reports flips/s over the
+    rounds, the time of sync + resize + init per round and the archive of the
+    best rank found per format."""
+    import torch
+    from paper_2511_20317_amd import explore, tsf
+    q = args.walks // 4
+    groups = [(tsf.init_scheme(*f), q, f[0] * f[1] * f[2] + 8, 0)
+              for f in [(2, 2, 2), (2, 2, 3), (2, 3, 3), (3, 3, 3)]]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    archive, stats = explore.explore(ctx, groups, rounds=args.steps, iters=args.iters,
+                                     capacity=128, base_seed=0, plateau=20000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    flips = sum(s["flips"] for s in stats)
+    arch = {"%d,%d,%d" % k: v[0] for k, v in sorted(archive.items())}
+    bad = sum(int(tsf.verify(s) != 0) for _, s in archive.values())
+    return {"flips_per_s": flips / wall, "wall_s": wall, "rounds": stats,
+            "formats_in_archive": len(arch), "archive_best_rank": arch,
+            "archive_schemes_failing_brent": bad}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,7 +357,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=100000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter scale)")
-    ap.add_argument("--workload", default="333", choices=["333", "mixed", "large", "additions"],
+    ap.add_argument("--workload", default="333",
+                    choices=["333", "mixed", "large", "additions", "explore"],
                     help="333: the (3,3,3) benchmark; mixed / large / additions: the other "
                          "workloads")
     ap.add_argument("--learned", action="store_true",
@@ -355,12 +382,16 @@ def main():
     torch.cuda.set_device(0)
     ctx = tsf.Context()
     if args.workload != "333":
-        res = {"mixed": run_mixed, "large": run_large,
-               "additions": run_additions}[args.workload](ctx, args)
+        res = {"mixed": run_mixed, "large": run_large, "additions": run_additions,
+               "explore": run_explore}[args.workload](ctx, args)
         if args.workload == "mixed":
             value = res["ternary"]["flips_per_s"]
             desc = ("131,072 walks over (3,3,4), (3,4,5), (4,4,4), (4,4,5) in one launch, "
                     "ternary then Z2")
+        elif args.workload == "explore":
+            value = res["flips_per_s"]
+            desc = ("exploratory search: 4 x %d walks from (2,2,2), (2,2,3), (2,3,3), (3,3,3), "
+                    "rounds of walks, population sync and resize" % (args.walks // 4))
         elif args.workload == "additions":
             value = res["flips_per_s"]
             desc = ("65,536 (3,3,3) walks minimising naive additions at fixed rank from the best "
@@ -371,7 +402,8 @@ def main():
                     "p-1 and extend back between rounds")
         out = {"metric": "flips/sec on 1 GPU", "value": value, "unit": "flips/s", "n_gpus": 1,
                "steps": args.steps, "warmup": 0, "higher_is_better": True, "scaling": "weak",
-               "vs_baseline": None, "dtype": "u64" if args.workload == "large" else "u32",
+               "vs_baseline": None,
+               "dtype": "u64" if args.workload in ("large", "explore") else "u32",
                "data": "synthetic", "config": {"workload": desc, "walks": args.walks,
                                                "iters_per_step": args.iters},
                "results": res}

@@ -355,9 +355,9 @@ tsf_status tsf_invariants_batch(const tsf_walk_batch *b, int32_t which, uint8_t 
  * walks of a batch (walks flagged invalid excluded) and, per format, the walk
  * with the best rank (ties: the lowest walk id).  table (device, >= slots
  * entries) receives them in ascending (m, n, p) order, *n_entries (device)
- * their number.  work (device, 2*slots + 1 uint64) is scratch; slots bounds
- * the number of distinct formats (more are dropped and counted in the last
- * word of work).  Async on the stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
+ * their number.  work (device, 2*slots + 1 uint64) is scratch; slots
+ * (1..4096) bounds the number of distinct formats (more are dropped and
+ * counted in the last word of work).  Async on the stream.  Errors: TSF_E_ARG, TSF_E_DEVICE. */
 typedef struct {
     int32_t m, n, p, rank;
     int64_t walk;

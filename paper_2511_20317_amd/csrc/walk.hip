@@ -342,25 +342,35 @@ __global__ void best_insert_kernel(const tsf_walk_header *hdr, int32_t n_walks,
     atomicAdd(overflow, 1);
 }
 
-// One workgroup: the occupied slots in ascending (m, n, p) order -> table.
+// One workgroup: the occupied slots in ascending (m, n, p) order -> table
+// (each slot's position = the number of smaller formats, counted over a copy
+// of the format keys in LDS; empty slots hold the largest key).
+constexpr int kMaxSlots = 4096;
 __global__ void __launch_bounds__(256) best_compact_kernel(const unsigned long long *keys,
                                                            const unsigned long long *vals,
                                                            int slots, tsf_best_entry *table,
                                                            int32_t *n_entries)
 {
+    __shared__ uint32_t ord[kMaxSlots];
+    __shared__ int32_t used;
+    if (threadIdx.x == 0) used = 0;
+    __syncthreads();
+    int mine = 0;
     for (int q = threadIdx.x; q < slots; q += blockDim.x) {
         const unsigned long long k = keys[q];
-        if (!k) continue;
-        const unsigned long long ord = ((k >> 8) & 0xFF) << 16 | ((k >> 16) & 0xFF) << 8 |
-                                       ((k >> 24) & 0xFF);
+        ord[q] = k ? (uint32_t)(((k >> 8) & 0xFF) << 16 | ((k >> 16) & 0xFF) << 8 |
+                                ((k >> 24) & 0xFF))
+                   : 0xFFFFFFFFu;
+        mine += k != 0;
+    }
+    atomicAdd(&used, mine);
+    __syncthreads();
+    for (int q = threadIdx.x; q < slots; q += blockDim.x) {
+        const uint32_t o = ord[q];
+        if (o == 0xFFFFFFFFu) continue;
         int pos = 0;
-        for (int x = 0; x < slots; ++x) {
-            const unsigned long long kx = keys[x];
-            if (!kx) continue;
-            const unsigned long long ox = ((kx >> 8) & 0xFF) << 16 | ((kx >> 16) & 0xFF) << 8 |
-                                          ((kx >> 24) & 0xFF);
-            pos += ox < ord;
-        }
+        for (int x = 0; x < slots; ++x) pos += ord[x] < o;
+        const unsigned long long k = keys[q];
         tsf_best_entry e;
         e.m = (int32_t)((k >> 8) & 0xFF);
         e.n = (int32_t)((k >> 16) & 0xFF);
@@ -369,11 +379,7 @@ __global__ void __launch_bounds__(256) best_compact_kernel(const unsigned long l
         e.walk = (int64_t)(vals[q] & 0xFFFFFFFFull);
         table[pos] = e;
     }
-    if (threadIdx.x == 0) {
-        int c = 0;
-        for (int x = 0; x < slots; ++x) c += keys[x] != 0;
-        *n_entries = c;
-    }
+    if (threadIdx.x == 0) *n_entries = used;
 }
 
 // Algorithm 2 on every walk (one wavefront per walk): the walk's current or
@@ -1074,7 +1080,8 @@ tsf_status tsf_population_best(const tsf_walk_batch *b, tsf_best_entry *table, i
 {
     tsf_status st = check_batch(b);
     if (st) return st;
-    if (slots < 1 || slots > 65536) return tsf_fail(TSF_E_ARG, "slots %d outside [1, 65536]", slots);
+    if (slots < 1 || slots > kMaxSlots)
+        return tsf_fail(TSF_E_ARG, "slots %d outside [1, %d]", slots, kMaxSlots);
     if (!table || !n_entries || !work) return tsf_fail(TSF_E_ARG, "null table or workspace");
     hipStream_t s = (hipStream_t)hip_stream;
     unsigned long long *keys = (unsigned long long *)work, *vals = keys + slots;

@@ -27,7 +27,7 @@ def _archive_update(archive, batch, table, count, hdr):
 
 
 def explore(ctx, groups, rounds, iters, capacity, base_seed=0, t_resize=tsf.ALWAYS, plateau=20000,
-            r_cap_extra=8, slots=256, walk_kw=None):
+            r_cap_extra=8, slots=4096, walk_kw=None):
     """groups: start schemes as for WalkBatch (one mode).  Returns the archive
     {format: (best rank, Scheme)} and per-round statistics."""
     a = tsf.WalkBatch(groups, capacity=capacity, rec_cap=4)

@@ -488,7 +488,7 @@ class WalkBatch:
                                          C.c_void_p(sums.data_ptr()), self._stream()))
         return ranks, sums
 
-    def population_best(self, slots=256):
+    def population_best(self, slots=4096):
         """Per distinct format, the walk with the best rank (ties: lowest id),
         ascending (m, n, p): (device table of BEST_ENTRY_DTYPE records as a
         uint8 tensor, device int32 count) -- tsf_population_best."""
