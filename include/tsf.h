@@ -135,6 +135,34 @@ tsf_status tsf_meta_merge(const tsf_scheme *a, const tsf_scheme *b, int32_t axis
  * Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_CAPACITY. */
 tsf_status tsf_meta_product(const tsf_scheme *a, const tsf_scheme *b, tsf_scheme *out);
 
+/* Ternary lifting (Sec. 3.10.1): signs for the non-zero coefficients of a Z2
+ * scheme (entries 0/1, mode TSF_Z2) such that the Brent equations hold over
+ * the integers.  An exhaustive search on the GPU: per term the first non-zero
+ * entry of u and of v is +1 and the other non-zero entries (u ascending, then
+ * v, then w) are the term's free signs, bit i of the term's pattern meaning
+ * entry i is -1; assignments are ordered by the terms' patterns (term 0 most
+ * significant); the search returns the first lifting in this order.  The
+ * patterns of the leading terms split the space into at most max_subtrees
+ * subtrees searched in parallel, each for at most max_nodes term
+ * assignments.  res->status: 1 found (the first lifting in the order), 2
+ * found (a valid lifting; a smaller subtree ran out of budget, so it may not
+ * be the first), 0 no lifting exists (every subtree searched to the end), -1
+ * unknown (none found, some subtree ran out of budget).  On 1 or 2, out
+ * (host, capacity >= rank) receives the ternary scheme.  Synchronous; uses
+ * the current device and temporary device memory.
+ * Errors: TSF_E_ARG, TSF_E_FORMAT, TSF_E_NOT_TERNARY, TSF_E_CAPACITY (more
+ * than 8192 equations, 512 terms or 40 free signs in a term), TSF_E_DEVICE. */
+typedef struct {
+    int32_t status;
+    int32_t prefix_terms;      /* leading terms whose patterns name a subtree   */
+    int64_t subtrees;
+    int64_t exhausted;         /* subtrees searched to the end                  */
+    int64_t subtree;           /* the subtree of the lifting returned, or -1    */
+} tsf_lift_result;
+
+tsf_status tsf_lift(const tsf_scheme *z2, int64_t max_nodes, int32_t max_subtrees,
+                    tsf_scheme *out, tsf_lift_result *res);
+
 /* Isotropy invariants (Sec. 3.7).  Each factor of term l is read as a matrix
  * (u: m x n, entry a_ij at row i, column j; v: n x p; w: p x m, entry c_ik at
  * row k, column i) and its rank taken over Q for ternary schemes, over GF(2)

@@ -709,6 +709,148 @@ int or_resize(const or_scheme *s, const or_scheme *best, int n_best, uint64_t se
     return applied;
 }
 
+/* Ternary lifting (Sec. 3.10.1): signs for the non-zero coefficients of a
+ * Z2 scheme such that the Brent equations hold over the integers.  Reading:
+ * an exhaustive search that returns the first solution in a fixed order
+ * (the paper uses a constraint solver; any solution is a valid lifting, the
+ * order only makes the answer unique).  Per term, the first non-zero entry of
+ * u and of v is +1 (any solution can be brought to this form, Sec. 3.6); the
+ * other non-zero entries -- u ascending, then v, then w -- are the term's free
+ * signs, bit i of the term's pattern x set meaning entry i is -1.  Terms are
+ * assigned in order, patterns ascending; after each term, every equation it
+ * touches must still be reachable: |target - partial sum| <= the number of
+ * later terms that touch it (each adds +-1).  Returns 1 with the scheme in
+ * *out, 0 when no lifting exists, -1 when max_nodes term assignments were
+ * tried first; *nodes counts them. */
+typedef struct {
+    const or_scheme *s;
+    int Lu, Lv, Lw;
+    int *nz[3];          /* per term and kind: the non-zero entries, ascending */
+    int cnt[OR_MAXT][3];
+    long *res, *rem;     /* per equation: target - partial sum; later contributors */
+    int8_t sign[OR_MAXT][3][OR_MAXL];
+    int64_t nodes, max_nodes;
+} lift_state;
+
+static int lift_free(const lift_state *L, int l)
+{
+    return L->cnt[l][0] - 1 + L->cnt[l][1] - 1 + L->cnt[l][2];
+}
+
+/* the pattern's signs into sign[l] */
+static void lift_pattern(lift_state *L, int l, long x)
+{
+    int bit = 0;
+    for (int X = 0; X < 3; ++X)
+        for (int q = 0; q < L->cnt[l][X]; ++q) {
+            int e = L->nz[X][l * OR_MAXL + q];
+            if (X < 2 && q == 0) {
+                L->sign[l][X][e] = 1;
+            } else {
+                L->sign[l][X][e] = ((x >> bit) & 1) ? -1 : 1;
+                ++bit;
+            }
+        }
+}
+
+/* add (dir = -1) or remove (+1) term l's products; returns 1 when every
+ * touched equation stays reachable (checked when adding) */
+static int lift_apply(lift_state *L, int l, int dir)
+{
+    int ok = 1;
+    for (int qa = 0; qa < L->cnt[l][0]; ++qa) {
+        int a = L->nz[0][l * OR_MAXL + qa];
+        for (int qb = 0; qb < L->cnt[l][1]; ++qb) {
+            int b = L->nz[1][l * OR_MAXL + qb];
+            for (int qc = 0; qc < L->cnt[l][2]; ++qc) {
+                int c = L->nz[2][l * OR_MAXL + qc];
+                long e = ((long)a * L->Lv + b) * L->Lw + c;
+                long prod = L->sign[l][0][a] * L->sign[l][1][b] * L->sign[l][2][c];
+                L->res[e] += dir * prod;
+                L->rem[e] += dir;
+                if (dir < 0 && (L->res[e] > L->rem[e] || -L->res[e] > L->rem[e])) ok = 0;
+            }
+        }
+    }
+    return ok;
+}
+
+static int lift_dfs(lift_state *L, int l)
+{
+    if (l == L->s->r) return 1;
+    long n_pat = 1L << lift_free(L, l);
+    for (long x = 0; x < n_pat; ++x) {
+        if (L->nodes >= L->max_nodes) return -1;
+        L->nodes++;
+        lift_pattern(L, l, x);
+        int ok = lift_apply(L, l, -1);
+        if (ok) {
+            int r = lift_dfs(L, l + 1);
+            if (r != 0) return r;   /* found (1) or out of budget (-1): keep the signs */
+        }
+        lift_apply(L, l, +1);
+    }
+    return 0;
+}
+
+int or_lift(const or_scheme *z2s, int64_t max_nodes, or_scheme *out, int64_t *nodes)
+{
+    const or_scheme *s = z2s;
+    int m = s->m, n = s->n, p = s->p;
+    lift_state *L = (lift_state *)calloc(1, sizeof(lift_state));
+    if (!L) return -2;
+    L->s = s;
+    L->Lu = m * n; L->Lv = n * p; L->Lw = p * m;
+    L->max_nodes = max_nodes;
+    long E = (long)L->Lu * L->Lv * L->Lw;
+    L->res = (long *)calloc((size_t)E, sizeof(long));
+    L->rem = (long *)calloc((size_t)E, sizeof(long));
+    for (int X = 0; X < 3; ++X) L->nz[X] = (int *)calloc((size_t)OR_MAXT * OR_MAXL, sizeof(int));
+    int lens[3] = { L->Lu, L->Lv, L->Lw };
+    int status = 0;
+    for (int l = 0; l < s->r; ++l)
+        for (int X = 0; X < 3; ++X) {
+            int c = 0;
+            for (int e = 0; e < lens[X]; ++e)
+                if (s->f[X][l][e] != 0) L->nz[X][l * OR_MAXL + c++] = e;
+            L->cnt[l][X] = c;
+            if (c == 0) status = -3;      /* a zero factor: not a scheme term */
+        }
+    for (long e = 0; e < E; ++e) {
+        long a = e / ((long)L->Lv * L->Lw), b = (e / L->Lw) % L->Lv, c = e % L->Lw;
+        int a1 = (int)(a / n), a2 = (int)(a % n), b1 = (int)(b / p), b2 = (int)(b % p);
+        int c1 = (int)(c / m), c2 = (int)(c % m);
+        L->res[e] = (a2 == b1 && b2 == c1 && c2 == a1) ? 1 : 0;
+    }
+    for (int l = 0; l < s->r && status == 0; ++l)
+        for (int qa = 0; qa < L->cnt[l][0]; ++qa)
+            for (int qb = 0; qb < L->cnt[l][1]; ++qb)
+                for (int qc = 0; qc < L->cnt[l][2]; ++qc) {
+                    long e = ((long)L->nz[0][l * OR_MAXL + qa] * L->Lv + L->nz[1][l * OR_MAXL + qb]) *
+                             L->Lw + L->nz[2][l * OR_MAXL + qc];
+                    L->rem[e]++;
+                }
+    if (status == 0) {
+        for (int l = 0; l < s->r; ++l)
+            if (lift_free(L, l) > 40) status = -3;   /* beyond any search here */
+    }
+    if (status == 0) status = lift_dfs(L, 0);
+    if (status == 1) {
+        memset(out, 0, sizeof(*out));
+        out->m = m; out->n = n; out->p = p; out->r = s->r; out->z2 = 0;
+        for (int l = 0; l < s->r; ++l)
+            for (int X = 0; X < 3; ++X)
+                for (int e = 0; e < lens[X]; ++e)
+                    out->f[X][l][e] = s->f[X][l][e] ? L->sign[l][X][e] : 0;
+    }
+    if (nodes) *nodes = L->nodes;
+    for (int X = 0; X < 3; ++X) free(L->nz[X]);
+    free(L->res);
+    free(L->rem);
+    free(L);
+    return status;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The walk: Algorithm 1 (RandomWalk kernel, Sec. 3.4.2)                     */
 /* ------------------------------------------------------------------------ */

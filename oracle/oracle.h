@@ -59,6 +59,7 @@ int  or_merge(const or_scheme *a, const or_scheme *b, int axis, or_scheme *out);
 int  or_product(const or_scheme *a, const or_scheme *b, or_scheme *out);
 int  or_resize(const or_scheme *s, const or_scheme *best, int n_best, uint64_t seed,
                int64_t round, uint64_t t_resize, int cap, or_scheme *out);
+int  or_lift(const or_scheme *z2s, int64_t max_nodes, or_scheme *out, int64_t *nodes);
 
 /* --- the walk (Algorithm 1) ------------------------------------------------ */
 typedef struct {

@@ -72,6 +72,7 @@ def lib():
         L.or_product.argtypes = [P(Scheme), P(Scheme), P(Scheme)]
         L.or_resize.argtypes = [P(Scheme), P(Scheme), C.c_int, C.c_uint64, C.c_int64,
                                 C.c_uint64, C.c_int, P(Scheme)]
+        L.or_lift.argtypes = [P(Scheme), C.c_int64, P(Scheme), P(C.c_int64)]
         L.or_normalise_term.argtypes = [P(Scheme), C.c_int]
         L.or_is_normalised.argtypes = [P(Scheme)]
         L.or_project.argtypes = [P(Scheme), C.c_int, C.c_int, P(Scheme)]
@@ -170,6 +171,14 @@ def merge(a: Scheme, b: Scheme, axis: int):
 def product(a: Scheme, b: Scheme):
     out = Scheme()
     return out if lib().or_product(C.byref(a), C.byref(b), C.byref(out)) == 0 else None
+
+
+def lift(z2s: Scheme, max_nodes: int = 10 ** 7):
+    """-> (status, ternary Scheme or None, nodes): 1 found, 0 none, -1 budget"""
+    out = Scheme()
+    nodes = C.c_int64(0)
+    st = lib().or_lift(C.byref(z2s), int(max_nodes), C.byref(out), C.byref(nodes))
+    return st, (out if st == 1 else None), int(nodes.value)
 
 
 def resize(s: Scheme, best, seed: int, rnd: int, t_resize: int, cap: int):

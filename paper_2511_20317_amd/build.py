@@ -27,7 +27,7 @@ def _units():
             units.append(([HIPCC] + HIP_FLAGS + ["-DTSFK_WIDE=%d" % wide, "-DTSFK_Z2=%d" % z2,
                                                   "-c", os.path.join(CSRC, "walk_inst.hip")],
                           "walk_inst_w%d_z%d.o" % (wide, z2)))
-    for src in ("walk.hip", "mlp.hip"):
+    for src in ("walk.hip", "mlp.hip", "lift.hip"):
         path = os.path.join(CSRC, src)
         if os.path.exists(path):
             units.append(([HIPCC] + HIP_FLAGS + ["-c", path], src.replace(".hip", ".o")))

@@ -80,6 +80,11 @@ BEST_ENTRY_DTYPE = np.dtype([("m", "<i4"), ("n", "<i4"), ("p", "<i4"), ("rank", 
                              ("walk", "<i8")])
 
 
+class LiftResultC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("prefix_terms", C.c_int32), ("subtrees", C.c_int64),
+                ("exhausted", C.c_int64), ("subtree", C.c_int64)]
+
+
 class Launch(C.Structure):
     _fields_ = [("lanes_per_walk", C.c_int32), ("waves_per_block", C.c_int32),
                 ("strategy", C.c_int32)]
@@ -151,6 +156,7 @@ def lib():
             ("tsf_format_slot", [C.c_int32, C.c_int32, C.c_int32]),
             ("tsf_scheme_invariants", [P(CScheme), C.c_void_p, P(InvariantsC)]),
             ("tsf_meta_swap", [P(CScheme), P(CScheme)]),
+            ("tsf_lift", [P(CScheme), C.c_int64, C.c_int32, P(CScheme), P(LiftResultC)]),
             ("tsf_meta_merge", [P(CScheme), P(CScheme), C.c_int32, P(CScheme)]),
             ("tsf_meta_product", [P(CScheme), P(CScheme), P(CScheme)]),
             ("tsf_population_best", [P(WalkBatchC), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -299,6 +305,21 @@ def meta_product(a: Scheme, b: Scheme) -> Scheme:
     check(lib().tsf_meta_product(C.byref(a.c()), C.byref(b.c()), C.byref(cs)))
     out._take(cs)
     return out
+
+
+def lift(z2: Scheme, max_nodes=1 << 20, max_subtrees=1 << 16):
+    """Ternary lifting of a Z2 scheme on the GPU (tsf_lift): returns (result
+    dict, ternary Scheme or None)."""
+    out = Scheme.empty(z2.m, z2.n, z2.p, max(z2.rank, 1), TSF_TERNARY)
+    cs = out.c()
+    res = LiftResultC()
+    check(lib().tsf_lift(C.byref(z2.c()), int(max_nodes), int(max_subtrees), C.byref(cs),
+                         C.byref(res)))
+    info = {k: int(getattr(res, k)) for k, _ in LiftResultC._fields_}
+    if res.status in (1, 2):
+        out._take(cs)
+        return info, out
+    return info, None
 
 
 def _poly(arr):
