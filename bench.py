@@ -340,6 +340,46 @@ def run_explore(ctx, args):
             "archive_schemes_failing_brent": bad}
 
 
+def run_lift(ctx, args):
+    """Ternary lifting (Sec. 3.10.1) of Z2 schemes found on the GPU: Z2 walks
+    of (2,2,3), (2,3,3) and (3,3,3) from the standard schemes (args.walks each,
+    5e4 iterations, untimed); the lowest-rank best schemes (up to 4 distinct
+    per format) are lifted with the GPU search (timed per scheme)."""
+    import torch
+    from paper_2511_20317_amd import tsf
+    out = {}
+    for fmt in [(2, 2, 3), (2, 3, 3), (3, 3, 3)]:
+        m, n, p = fmt
+        b = tsf.WalkBatch([(tsf.init_scheme(m, n, p, tsf.TSF_Z2), args.walks, m * n * p + 8, 0)],
+                          rec_cap=4)
+        b.init(ctx)
+        b.walk(ctx, tsf.walk_params(base_seed=5, max_iters=50000, plateau=20000), 50000)
+        hdr = b.headers()
+        low = int(hdr["best_rank"].min())
+        picked, seen = [], set()
+        for w in np.flatnonzero(hdr["best_rank"] == low):
+            s = b.scheme(int(w), "best", hdr)
+            key = s.U.tobytes() + s.V.tobytes() + s.W.tobytes()
+            if key not in seen:
+                seen.add(key)
+                picked.append(s)
+            if len(picked) == 4:
+                break
+        res = []
+        for s in picked:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info, t = tsf.lift(s, max_nodes=1 << 16, max_subtrees=1 << 16)
+            dt = time.perf_counter() - t0
+            res.append({"status": info["status"], "seconds": dt, "subtrees": info["subtrees"],
+                        "exhausted": info["exhausted"],
+                        "valid": (tsf.verify(t) == 0) if t is not None else None})
+            print("lift %s rank %d: status %d in %.2f s" % (fmt, low, info["status"], dt),
+                  file=sys.stderr, flush=True)
+        out["%d,%d,%d" % fmt] = {"z2_rank": low, "schemes": res}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,7 +398,7 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter scale)")
     ap.add_argument("--workload", default="333",
-                    choices=["333", "mixed", "large", "additions", "explore"],
+                    choices=["333", "mixed", "large", "additions", "explore", "lift"],
                     help="333: the (3,3,3) benchmark; mixed / large / additions: the other "
                          "workloads")
     ap.add_argument("--learned", action="store_true",
@@ -383,7 +423,7 @@ def main():
     ctx = tsf.Context()
     if args.workload != "333":
         res = {"mixed": run_mixed, "large": run_large, "additions": run_additions,
-               "explore": run_explore}[args.workload](ctx, args)
+               "explore": run_explore, "lift": run_lift}[args.workload](ctx, args)
         if args.workload == "mixed":
             value = res["ternary"]["flips_per_s"]
             desc = ("131,072 walks over (3,3,4), (3,4,5), (4,4,4), (4,4,5) in one launch, "
@@ -392,6 +432,9 @@ def main():
             value = res["flips_per_s"]
             desc = ("exploratory search: 4 x %d walks from (2,2,2), (2,2,3), (2,3,3), (3,3,3), "
                     "rounds of walks, population sync and resize" % (args.walks // 4))
+        elif args.workload == "lift":
+            value = None
+            desc = "ternary lifting of the best Z2 schemes of (2,2,3), (2,3,3), (3,3,3) walks"
         elif args.workload == "additions":
             value = res["flips_per_s"]
             desc = ("65,536 (3,3,3) walks minimising naive additions at fixed rank from the best "

@@ -281,7 +281,9 @@ tsf_status tsf_lift(const tsf_scheme *z2, int64_t max_nodes, int32_t max_subtree
                     hipMemcpy(s.data(), d_signs, s.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) {
                     st = tsf_fail(TSF_E_DEVICE, "lift replay failed");
                 } else {
+                    const int32_t out_cap = out->d.capacity;   // the caller's buffers
                     out->d = z2->d;
+                    out->d.capacity = out_cap;
                     out->d.mode = TSF_TERNARY;
                     int8_t *om[3] = {out->U, out->V, out->W};
                     for (int X = 0; X < 3; ++X)

@@ -68,3 +68,11 @@ def test_lift_matches_oracle(ctx):
             for g, zz in zip(got.live(), _to_tsf(z).live()):
                 assert np.array_equal(np.abs(g), zz), name
     assert none_seen >= 1
+
+
+def test_lift_input_capacity_larger_than_rank(ctx):
+    """The output keeps its own capacity when the input has spare rows."""
+    U, V, W = load_formula_scheme("strassen_formulas.txt")[3:]
+    z = tsf.Scheme(2, 2, 2, np.abs(U), np.abs(V), np.abs(W), tsf.TSF_Z2, capacity=40)
+    info, got = tsf.lift(z)
+    assert info["status"] == 1 and got.rank == 7 and tsf.verify(got) == 0
