@@ -925,6 +925,13 @@ struct Walker {
     __device__ int reduce(int &tr0, int &tr1)
     {
         int merges = 0;
+        if constexpr (IX) {
+            // the common case: neither modified term shares two factors with
+            // another term (six mask reads, no term loads)
+            const uint64_t ca = tr0 >= 0 ? two_shared(tr0) : 0ull;
+            const uint64_t cb = tr1 >= 0 ? two_shared(tr1) : 0ull;
+            if ((ca | cb) == 0) return 0;
+        }
         bool done0 = tr0 < 0;
         for (;;) {
             const int ia = done0 ? -1 : tr0, ib = tr1;
