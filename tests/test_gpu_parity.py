@@ -165,6 +165,50 @@ def test_config2_full_batch_sampled(ctx):
     assert (nv == 0).all()
 
 
+@pytest.mark.parametrize("mode", [tsf.TSF_TERNARY, tsf.TSF_Z2])
+def test_config3_full_batch_sampled(ctx, mode):
+    """Mixed formats in one launch at full size: 131,072 walks, 32,768 each of
+    (3,3,4), (3,4,5), (4,4,4), (4,4,5) from the standard schemes, ternary and
+    Z2; sampled walks of every format against the oracle."""
+    fmts = [(3, 3, 4), (3, 4, 5), (4, 4, 4), (4, 4, 5)]
+    groups = [(_std(*f, mode), 32768, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
+    prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
+    b = _run(ctx, groups, prm, 1500)
+    rng = np.random.default_rng(3)
+    walks = sorted({int(q * 32768 + x) for q in range(4) for x in rng.integers(0, 32768, 5)})
+    compare(b, run_oracle(groups, prm, walks, 1500), "cfg3 mode=%d" % mode)
+    assert (b.verify_device(which=1).cpu().numpy() == 0).all()
+
+
+def test_config5_full_batch_sampled(ctx):
+    """Large formats at full size: 32,768 walks each of (4,5,12), (5,6,10),
+    (6,7,9) (64-bit masks), sampled walks of every format against the oracle,
+    then a device project to p-1 of every walk checked against the oracle's
+    projection of its best scheme."""
+    from oracle import pyoracle as O
+    fmts = [(4, 5, 12), (5, 6, 10), (6, 7, 9)]
+    groups = [(_std(*f), 32768, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
+    prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
+    b = _run(ctx, groups, prm, 150, lanes=64, wpb=1)
+    rng = np.random.default_rng(5)
+    walks = sorted({int(q * 32768 + x) for q in range(3) for x in rng.integers(0, 32768, 3)})
+    ow = run_oracle(groups, prm, walks, 150, threads=9)
+    compare(b, ow, "cfg5")
+    assert (b.verify_device(which=1).cpu().numpy() == 0).all()
+    n = b.n_walks
+    small = tsf.WalkBatch.empty(n, b.capacity, tsf.TSF_TERNARY, max_len=63, rec_cap=4)
+    idx = np.concatenate([rng.integers(0, f[2], 32768) for f in fmts])
+    small.meta_from(b, 1, np.ones(n), np.full(n, 2), idx, r_cap_extra=8)
+    small.init(ctx)
+    _sync()
+    hdr = small.headers()
+    for w in walks:
+        ob = O.from_c(O.project(ow[w].best, 2, int(idx[w])))
+        got = small.scheme(w, "start", hdr)
+        for g, o in zip(got.live(), (ob["U"], ob["V"], ob["W"])):
+            assert np.array_equal(g, o), w
+
+
 def test_meta_project_extend_batch_then_walk(ctx):
     """Device project/extend of walked schemes equals the oracle's project /
     extend of its own (bit-identical) walked schemes; walks continued from the
