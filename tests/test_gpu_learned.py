@@ -154,3 +154,24 @@ def test_learned_scores_and_choices_at_first_iteration(ctx):
             continue
         best = max(logit[w, a] for a in valid)
         assert choice[w] == min(a for a in valid if logit[w, a] == best)
+
+
+def test_trained_network_ranks_held_out_flips(ctx):
+    """What training gains: on flips logged by uniform (3,3,3) walks, the
+    network trained by the GPU kernels ranks the flips that lead to a rank
+    drop within 1000 iterations above the others on held-out walks better
+    than chance and better than the untrained network (AUC)."""
+    from paper_2511_20317_amd import learn
+    s = tsf.init_scheme(3, 3, 3)
+    rec, idx, lab = learn.collect(ctx, s, 1024, 4000, 35, base_seed=500)
+    held, hidx, hlab = learn.collect(ctx, s, 512, 4000, 35, base_seed=90000)
+    rng = np.random.default_rng(0)
+    net = tsf.Mlp()
+    net.set_params(rng.standard_normal((512, 256)) * np.sqrt(2 / 64), np.zeros(256),
+                   rng.standard_normal((256, 256)) * np.sqrt(2 / 256), np.zeros(256),
+                   rng.standard_normal(256) * np.sqrt(1 / 256), np.zeros(1))
+    before = learn.evaluate(net, held, hidx, hlab)
+    learn.train(net, rec, idx, lab, 800, batch=4096, lr=1e-3)
+    after = learn.evaluate(net, held, hidx, hlab)
+    assert after["loss"] < before["loss"]
+    assert after["auc"] > 0.52 and after["auc"] > before["auc"] + 0.02, (before, after)
