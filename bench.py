@@ -158,7 +158,10 @@ def run_mixed(ctx, args):
         b = tsf.WalkBatch(groups, rec_cap=64)
         prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
         b.init(ctx)
-        tuned = b.autotune(ctx, prm, trial_iters=200)
+        # tune on the state after a short walk: the first iterations from the
+        # standard schemes (many equal factors) are not typical of the run
+        b.walk(ctx, prm, 2000, 32, 1, 2)
+        tuned = b.autotune(ctx, prm, trial_iters=1000)
         b.init(ctx)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -380,6 +383,41 @@ def run_lift(ctx, args):
     return out
 
 
+def time_to_rank_fine(ctx, args, target=23, round_iters=1000, limit_s=60.0):
+    """Time to the target rank with rounds of round_iters iterations: a fresh
+    batch of the (3,3,3) workload is walked round by round (the best rank is
+    read after each round) until some walk reaches the target; the schemes are
+    then Brent-checked on the GPU.  The wall time runs from the first round's
+    launch to the end of the round that reached the target."""
+    import torch
+    from paper_2511_20317_amd import tsf
+    b = tsf.WalkBatch([(tsf.init_scheme(3, 3, 3), args.walks, 35, target)], rec_cap=32)
+    prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
+    b.init(ctx)
+    best_col = b.hdr.view(torch.int32).view(args.walks, 40)[:, 7]
+    ladder, done = {}, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        b.walk(ctx, prm, round_iters, args.lanes, args.wpb, args.strategy)
+        done += round_iters
+        best = int(best_col.min().item())
+        now = time.perf_counter() - t0
+        for rank in (26, 25, 24, 23):
+            if best <= rank and rank not in ladder:
+                ladder[rank] = {"s": now, "iterations": done}
+        if best <= target or now >= limit_s or done >= 1000000:
+            break
+    hdr = b.headers()
+    hit = np.flatnonzero(hdr["best_rank"] <= target)
+    nv = b.verify_device(1).cpu().numpy()
+    return {"round_iters": round_iters, "time_to_rank_s": {str(k): v["s"] for k, v in ladder.items()},
+            "iterations_to_rank": {str(k): v["iterations"] for k, v in ladder.items()},
+            "time_to_rank_23_s": ladder[target]["s"] if target in ladder else None,
+            "walks_at_target": int(hit.size),
+            "walks_at_target_failing_brent": int((nv[hit] != 0).sum()) if hit.size else 0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -560,6 +598,7 @@ def main():
         "attempts_per_iteration": cnt["attempts"] / iters,
         "fallback_rate": cnt["fallbacks"] / iters,
         "best_schemes_failing_brent": bad_total,
+        "time_to_rank_23_fine": time_to_rank_fine(ctx, args, target),
         "learned_vs_uniform": None,
     }
     if args.learned:

@@ -554,29 +554,40 @@ struct Walker {
     // ------------------------------------------------------------------ TP
     // Candidate partners of (i, X): lane-parallel over the terms, one ballot
     // per slot and role.  m0/m1: role 0/1 masks (bit = lane of slot q).
+    // Factor X of every slot is read first, at an index clamped to the walk's
+    // rows, so that the reads issue back to back; the validity of the two
+    // roles is evaluated only when some lane of the group has a match.
     __device__ void candidates_tp(int i, int X, uint64_t (&m0)[S], uint64_t (&m1)[S], int &n0,
                                   int &n1) const
     {
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
-        const TV<T> xi = ld(i, X), Ai = ld(i, A), Bi = ld(i, B);
+        const TV<T> xi = ld(i, X);
+        int sg[S];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int k = q * G + gl;
+            const TV<T> xk = ld(k < cap2 ? k : cap2 - 1, X);
+            sg[q] = (k < r && k != i) ? rel(xi, xk, X) : 0;
+            any |= sg[q] != 0;
+        }
         n0 = n1 = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) m0[q] = m1[q] = 0;
+        if (!gballot(any)) return;
+        const TV<T> Ai = ld(i, A), Bi = ld(i, B);
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             bool v0 = false, v1 = false;
-            if (q * G < r) {
+            if (sg[q] != 0) {
                 const int k = q * G + gl;
-                if (k < r && k != i) {
-                    const int sg = rel(xi, ld(k, X), X);
-                    if (sg != 0) {
-                        const TV<T> Ak = ld(k, A), Bk = ld(k, B);
-                        TV<T> o1, o2;
-                        const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
-                        const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
-                        const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
-                        v0 = a1 && b1 && keep;
-                        v1 = a2 && b2 && keep;
-                    }
-                }
+                const TV<T> Ak = ld(k, A), Bk = ld(k, B);
+                TV<T> o1, o2;
+                const bool a1 = axpy(sg[q], Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
+                const bool a2 = axpy(sg[q], Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
+                const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
+                v0 = a1 && b1 && keep;
+                v1 = a2 && b2 && keep;
             }
             m0[q] = gballot(v0);
             m1[q] = gballot(v1);
@@ -837,23 +848,41 @@ struct Walker {
             kb = first_merge(cb, tb);
             return;
         }
+        // U slots per round, their terms read before any is compared (indexes
+        // clamped to the walk's rows), so the reads of a round overlap
+        constexpr int U = 2;
         const int qend = (wave_max_r() + G - 1) / G;
 #pragma unroll 1
-        for (int q = 0; q < qend; ++q) {
-            const int kk = q * G + gl;
-            const bool live = kk < r;
-            TV<T> tk[3];
-            load_term(live ? kk : 0, tk);
-            bool oka = live && ia >= 0 && kk != ia && shares_two(ta, tk);
-            bool okb = live && ib >= 0 && kk != ib && shares_two(tb, tk);
-            if (__ballot(oka || okb)) {
-                TV<T> o;
-                oka = oka && merge_kind(ta, tk, o) >= 0;
-                okb = okb && merge_kind(tb, tk, o) >= 0;
+        for (int q0 = 0; q0 < qend; q0 += U) {
+            TV<T> tk[U][3];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int kk = (q0 + u) * G + gl;
+                load_term(kk < cap2 ? kk : cap2 - 1, tk[u]);
             }
-            const uint64_t ma = gballot(oka), mb = gballot(okb);
-            if (ka < 0 && ma) ka = q * G + __builtin_ctzll(ma);
-            if (kb < 0 && mb) kb = q * G + __builtin_ctzll(mb);
+            bool oka[U], okb[U], any = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int kk = (q0 + u) * G + gl;
+                const bool live = kk < r;
+                oka[u] = live && ia >= 0 && kk != ia && shares_two(ta, tk[u]);
+                okb[u] = live && ib >= 0 && kk != ib && shares_two(tb, tk[u]);
+                any |= oka[u] || okb[u];
+            }
+            if (__ballot(any)) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    TV<T> o;
+                    oka[u] = oka[u] && merge_kind(ta, tk[u], o) >= 0;
+                    okb[u] = okb[u] && merge_kind(tb, tk[u], o) >= 0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t ma = gballot(oka[u]), mb = gballot(okb[u]);
+                if (ka < 0 && ma) ka = (q0 + u) * G + __builtin_ctzll(ma);
+                if (kb < 0 && mb) kb = (q0 + u) * G + __builtin_ctzll(mb);
+            }
         }
     }
 

@@ -272,7 +272,11 @@ def test_autotune_leaves_state_and_keeps_parity(ctx):
     before = (b.hdr.clone(), b.cur.clone(), b.best.clone())
     chosen = b.autotune(ctx, prm, trial_iters=300)
     _sync()
-    assert chosen[0] in (8, 16, 32, 64) and chosen[2] in (1, 2)
+    # one of the autotuner's candidates (capacity 35: strategies 3 and 1 with
+    # 4, 8 or 16 lanes, strategy 2 with 16, 32 or 64; 1, 2 or 4 walk groups)
+    cands = {(g, w, s) for w in (1, 2, 4) for s in (3, 1) for g in (4, 8, 16)}
+    cands |= {(g, w, 2) for w in (1, 2, 4) for g in (16, 32, 64)}
+    assert tuple(chosen) in cands
     assert all((x == y).all() for x, y in zip(before, (b.hdr, b.cur, b.best)))
     b.walk(ctx, prm, 2500)  # default launch -> the tuned configuration
     _sync()
