@@ -160,7 +160,7 @@ def run_mixed(ctx, args):
         b.init(ctx)
         # tune on the state after a short walk: the first iterations from the
         # standard schemes (many equal factors) are not typical of the run
-        b.walk(ctx, prm, 2000, 32, 1, 2)
+        b.walk(ctx, prm, 2000)
         tuned = b.autotune(ctx, prm, trial_iters=1000)
         b.init(ctx)
         torch.cuda.synchronize()

@@ -306,7 +306,7 @@ typedef struct {
 } tsf_walk_batch;
 
 /* Launch configuration.  strategy: 1 = attempt-parallel (each lane of a walk
- * evaluates a different random flip attempt; capacity <= 64 only),
+ * evaluates a different random flip attempt; capacity <= 128 only),
  * 2 = term-parallel (the lanes of a walk split its terms; any capacity),
  * 3 = indexed attempt-parallel (strategy 1 over a match index kept in LDS:
  * per term and factor kind, a mask of the terms with an equal factor;
@@ -316,7 +316,8 @@ typedef struct {
  * term-parallel one).  waves_per_block: 1..4.  A zero field lets the library
  * choose (a launch chosen by tsf_autotune for batches of this shape, else
  * strategy 3 with 8 lanes and 1 wavefront per workgroup up to capacity 64,
- * strategy 2 with 64 lanes and 4 wavefronts beyond).
+ * strategy 1 with the same shape up to capacity 128 when max_len <= 32,
+ * strategy 2 with 64 lanes and 4 wavefronts otherwise).
  * Results never depend on it. */
 typedef struct {
     int32_t lanes_per_walk;

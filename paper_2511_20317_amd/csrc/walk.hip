@@ -754,11 +754,18 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (b->log && b->log_cap < 0) return tsf_fail(TSF_E_ARG, "log_cap < 0");
     int strategy = launch ? launch->strategy : 0;
     if (strategy < 0 || strategy > 3) return tsf_fail(TSF_E_ARG, "strategy %d not in 0..3", strategy);
-    if (strategy == 0) strategy = b->capacity <= 64 ? 3 : 2;
+    // default: the indexed strategy up to 64 terms; the plain attempt-parallel
+    // one up to 128 terms of 32-bit factors (with 64-bit factors its 8 walks
+    // per wavefront would hold 48 KiB of LDS per wavefront at 128 terms);
+    // the term-parallel one beyond
+    if (strategy == 0)
+        strategy = b->capacity <= 64 ? 3 : (b->capacity <= 128 && b->max_len <= 32 ? 1 : 2);
     const bool ap = strategy == 1 || strategy == 3;
     const bool ix = strategy == 3;
-    if (ap && b->capacity > 64)
-        return tsf_fail(TSF_E_CAPACITY, "the attempt-parallel strategies need capacity <= 64");
+    if (ix && b->capacity > 64)
+        return tsf_fail(TSF_E_CAPACITY, "the indexed strategy needs capacity <= 64");
+    if (ap && b->capacity > 128)
+        return tsf_fail(TSF_E_CAPACITY, "the attempt-parallel strategy needs capacity <= 128");
     int g = launch && launch->lanes_per_walk ? launch->lanes_per_walk : (ap ? 8 : 64);
     int wpb = launch && launch->waves_per_block ? launch->waves_per_block : (ap ? 1 : 4);
     if (g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
@@ -768,8 +775,9 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (ap && g == 64)
         return tsf_fail(TSF_E_ARG, "the attempt-parallel strategies use 4 to 32 lanes per walk");
     if (wpb < 1 || wpb > 4) return tsf_fail(TSF_E_ARG, "waves_per_block %d not in 1..4", wpb);
-    // term slots per lane (the term-parallel kernels only)
-    const int s = ap ? 1 : slots_for(b->capacity, g);
+    // term slots per lane (term-parallel kernels), or 64-bit words of a
+    // partner set (attempt-parallel kernels)
+    const int s = ap ? (b->capacity > 64 ? 2 : 1) : slots_for(b->capacity, g);
     if (s < 0)
         return tsf_fail(TSF_E_CAPACITY, "capacity %d needs more than 8 slots at %d lanes/walk",
                         b->capacity, g);
@@ -895,8 +903,8 @@ tsf_status tsf_autotune(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk
     if (!ok) return tsf_fail(TSF_E_DEVICE, "autotuner snapshot failed");
     std::vector<tsf_launch> cands;
     for (int wpb : {1, 2, 4}) {
-        if (b->capacity <= 64)
-            for (int st : {3, 1})
+        for (int st : {3, 1})
+            if (b->capacity <= (st == 3 ? 64 : 128))
                 for (int g : {4, 8, 16}) cands.push_back(tsf_launch{g, wpb, st});
         for (int g : {16, 32, 64}) cands.push_back(tsf_launch{g, wpb, 2});
     }

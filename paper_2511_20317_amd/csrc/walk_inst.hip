@@ -29,11 +29,17 @@ KernelFn pick_s(int s)
     }
 }
 
-// attempt-parallel kernels (schemes of at most 64 terms), plain or indexed
+// attempt-parallel kernels: indexed (at most 64 terms), or plain with
+// partner sets of s = 1 or 2 words (at most 64 or 128 terms)
 template <int G>
-KernelFn pick_ap(bool ix)
+KernelFn pick_ap(bool ix, int s)
 {
-    return ix ? walk_kernel<G, 1, Word, kZ2, true, true> : walk_kernel<G, 1, Word, kZ2, true, false>;
+    if (ix) return s == 1 ? walk_kernel<G, 1, Word, kZ2, true, true> : nullptr;
+    switch (s) {
+    case 1: return walk_kernel<G, 1, Word, kZ2, true, false>;
+    case 2: return walk_kernel<G, 2, Word, kZ2, true, false>;
+    default: return nullptr;
+    }
 }
 
 #define TSF_CAT2(a, b, c) pick_kernel_w##a##_z##b##c
@@ -44,10 +50,10 @@ KernelFn TSF_CAT(TSFK_WIDE, TSFK_Z2)(int g, int s, int strategy)
     if (strategy == 1 || strategy == 3) {
         const bool ix = strategy == 3;
         switch (g) {
-        case 4: return pick_ap<4>(ix);
-        case 8: return pick_ap<8>(ix);
-        case 16: return pick_ap<16>(ix);
-        case 32: return pick_ap<32>(ix);
+        case 4: return pick_ap<4>(ix, s);
+        case 8: return pick_ap<8>(ix, s);
+        case 16: return pick_ap<16>(ix, s);
+        case 32: return pick_ap<32>(ix, s);
         default: return nullptr;
         }
     }

@@ -21,12 +21,12 @@
 // lane G-1 the per-iteration gate block, so the draws run in parallel and a
 // skipped draw never shifts the stream.
 //
-// Two strategies search for a flip; both take the first attempt (in attempt
+// Three strategies search for a flip; all take the first attempt (in attempt
 // order) that has a valid partner, so their results are identical:
-//  * attempt-parallel (AP, schemes of at most 64 terms): each lane evaluates
-//    one random attempt (term i, factor kind X) against all terms -- a match
-//    scan over the X factors (two terms per LDS read), then the validity of
-//    the two roles for the few matches only;
+//  * attempt-parallel (AP, schemes of at most 64*S terms, S = 1 or 2 words
+//    per partner set): each lane evaluates one random attempt (term i, factor
+//    kind X) against all terms -- a match scan over the X factors (two terms
+//    per LDS read), then the validity of the two roles for the few matches;
 //  * term-parallel (TP, any size): attempts run one after another and the G
 //    lanes split the terms (slot q of lane l is term q*G + l), with one group
 //    ballot per slot and role;
@@ -151,9 +151,60 @@ __device__ __forceinline__ int kth_bit(uint64_t m, int c)
     return __builtin_ctzll(m);
 }
 
+// A set of term indexes below 64*NW, one bit per term (word q holds terms
+// 64q .. 64q+63); the attempt-parallel partner sets
+template <int NW>
+struct TermSet {
+    uint64_t w[NW];
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) w[q] = 0;
+    }
+    __device__ __forceinline__ bool any() const
+    {
+        uint64_t o = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) o |= w[q];
+        return o != 0;
+    }
+    __device__ __forceinline__ int count() const
+    {
+        int c = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) c += __builtin_popcountll(w[q]);
+        return c;
+    }
+    // the c-th (0-based) member in ascending order (the set has more than c)
+    __device__ __forceinline__ int kth(int c) const
+    {
+        if constexpr (NW == 1) {
+            return kth_bit(w[0], c);
+        } else {
+            int k = -1;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const int pc = __builtin_popcountll(w[q]);
+                if (k < 0) {
+                    if (c < pc)
+                        k = 64 * q + kth_bit(w[q], c);
+                    else
+                        c -= pc;
+                }
+            }
+            return k;
+        }
+    }
+};
+
 template <int G, int S, typename T, bool Z2, bool AP, bool IX>
 struct Walker {
     static_assert(!IX || AP, "the match index extends the attempt-parallel strategy");
+    // attempt-parallel kernels: S is the number of 64-bit words of a partner
+    // set (capacity up to 64*S); the indexed strategy keeps one word
+    static_assert(!AP || S == 1 || (S == 2 && !IX), "attempt-parallel partner sets of 1 or 2 words");
+    static constexpr int NW = AP ? S : 1;
+    using PSet = TermSet<NW>;
     // group geometry
     int gl;      // lane within the group
     int gshift;  // first lane of the group within the wavefront
@@ -613,53 +664,63 @@ struct Walker {
     }
 
     // ------------------------------------------------------------------ AP
-    // Partners of (i, X) for this lane alone, over all r <= 64 terms: bit k of
-    // m0/m1 is set when (k, role 0/1) is a valid flip partner.  The match
-    // scan runs to the batch capacity (a wave-uniform bound, so the loop
-    // counter and the bit constants stay scalar) and masks terms >= r.
-    __device__ void candidates_ap(int i, int X, uint64_t &m0, uint64_t &m1) const
+    // Partners of (i, X) for this lane alone, over all r <= 64*NW terms:
+    // member k of m0/m1 when (k, role 0/1) is a valid flip partner.  The
+    // match scan runs to the batch capacity (a wave-uniform bound, so the loop
+    // counter and the bit constants stay scalar; 32 terms per partial mask)
+    // and drops terms >= r.
+    __device__ void candidates_ap(int i, int X, PSet &m0, PSet &m1) const
     {
         const TV<T> xi = ld(i, X);
-        uint64_t match;
+        PSet match;
         if constexpr (IX) {
-            match = mk[X * cap2 + i];
+            match.w[0] = mk[X * cap2 + i];
         } else {
-        const T nsi = (!Z2 && X == 2) ? (xi.s ^ xi.d) : xi.s;  // accepted signs besides xi.s
-        const T *col = lds + idx(0, X);
-        const int kend = scan_end;  // even, wave-uniform
-        uint32_t lo = 0, hi = 0;
-        int k = 0;
-        for (; k < kend && k < 32; k += 2) {
-            const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2], s1 = col[2 * k + 3];
-            const uint32_t b0 = 1u << k, b1 = 2u << k;
-            lo |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
-            lo |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
+            const T nsi = (!Z2 && X == 2) ? (xi.s ^ xi.d) : xi.s;  // accepted signs besides xi.s
+            const T *col = lds + idx(0, X);
+            const int kend = scan_end;  // even, wave-uniform
+            uint32_t part[2 * NW];
+            int k = 0;
+#pragma unroll
+            for (int c = 0; c < 2 * NW; ++c) {
+                part[c] = 0;
+                for (; k < kend && k < 32 * (c + 1); k += 2) {
+                    const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2],
+                            s1 = col[2 * k + 3];
+                    const uint32_t b0 = 1u << (k - 32 * c), b1 = 2u << (k - 32 * c);
+                    part[c] |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
+                    part[c] |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const int lo = 64 * q;
+                const uint64_t live = r - lo >= 64 ? ~0ull : (r > lo ? (1ull << (r - lo)) - 1 : 0ull);
+                const uint64_t self = (i >> 6) == q ? 1ull << (i & 63) : 0ull;
+                match.w[q] = (((uint64_t)part[2 * q + 1] << 32) | part[2 * q]) & live & ~self;
+            }
         }
-        for (; k < kend; k += 2) {
-            const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2], s1 = col[2 * k + 3];
-            const uint32_t b0 = 1u << (k - 32), b1 = 2u << (k - 32);
-            hi |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
-            hi |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
-        }
-        match = ((uint64_t)hi << 32) | lo;
-        match &= (r >= 64 ? ~0ull : ((1ull << r) - 1)) & ~(1ull << i);
-        }
-        m0 = m1 = 0;
-        if (match == 0) return;
+        m0.clear();
+        m1.clear();
+        if (!match.any()) return;
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
         const TV<T> Ai = ld(i, A), Bi = ld(i, B);
-        for (uint64_t mm = match; mm; mm &= mm - 1) {
-            const int kk = __builtin_ctzll(mm);
-            const int sg = (Z2 || ld(kk, X).s == xi.s) ? 1 : -1;
-            const TV<T> Ak = ld(kk, A), Bk = ld(kk, B);
-            TV<T> o1, o2;
-            const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
-            const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
-            // a valid sum or difference is zero exactly when the supports
-            // agree; the additions objective admits no such flip
-            const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
-            m0 |= (uint64_t)(a1 && b1 && keep) << kk;
-            m1 |= (uint64_t)(a2 && b2 && keep) << kk;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            for (uint64_t mm = match.w[q]; mm; mm &= mm - 1) {
+                const int kb = __builtin_ctzll(mm);
+                const int kk = 64 * q + kb;
+                const int sg = (Z2 || ld(kk, X).s == xi.s) ? 1 : -1;
+                const TV<T> Ak = ld(kk, A), Bk = ld(kk, B);
+                TV<T> o1, o2;
+                const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
+                const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
+                // a valid sum or difference is zero exactly when the supports
+                // agree; the additions objective admits no such flip
+                const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
+                m0.w[q] |= (uint64_t)(a1 && b1 && keep) << kb;
+                m1.w[q] |= (uint64_t)(a2 && b2 && keep) << kb;
+            }
         }
     }
 
@@ -687,9 +748,11 @@ struct Walker {
                 }
                 const int i = (int)below(w0, (uint32_t)r);
                 const int X = (int)below(w1, 3u);
-                uint64_t m0 = 0, m1 = 0;
+                PSet m0, m1;
+                m0.clear();
+                m1.clear();
                 if (active) candidates_ap(i, X, m0, m1);
-                const int n0 = popc64(m0), n = n0 + popc64(m1);
+                const int n0 = m0.count(), n = n0 + m1.count();
                 const uint64_t ok = gballot(n > 0);
                 if (ok) {
                     const int win = __builtin_ctzll(ok);
@@ -698,7 +761,7 @@ struct Walker {
                         int c = (int)below(w2, (uint32_t)n);
                         const int role = c >= n0;
                         if (role) c -= n0;
-                        const int j = kth_bit(role ? m1 : m0, c);
+                        const int j = (role ? m1 : m0).kth(c);  // one search, on the chosen set
                         pick = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)X << 16) |
                                ((uint32_t)role << 18);
                     }
@@ -783,9 +846,11 @@ struct Walker {
             int p = p0 + q;
             if (p >= npairs) p -= npairs;
             const int i = p / 3, X = p - 3 * i;
-            uint64_t m0 = 0, m1 = 0;
+            PSet m0, m1;
+            m0.clear();
+            m1.clear();
             if (q < npairs) candidates_ap(i, X, m0, m1);
-            const int n0 = popc64(m0), n = n0 + popc64(m1);
+            const int n0 = m0.count(), n = n0 + m1.count();
             const uint64_t ok = gballot(n > 0);
             if (ok) {
                 const int win = __builtin_ctzll(ok);
@@ -794,7 +859,7 @@ struct Walker {
                     int c = (int)below(w.x[1], (uint32_t)n);
                     const int role = c >= n0;
                     if (role) c -= n0;
-                    const int j = kth_bit(role ? m1 : m0, c);
+                    const int j = (role ? m1 : m0).kth(c);  // one search, on the chosen set
                     packed = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)X << 16) |
                              ((uint32_t)role << 18);
                 }
@@ -1236,14 +1301,16 @@ struct Walker {
             update_scan_end();
             const int i = (int)below(pb.x[0], (uint32_t)r);
             const int X = (int)below(pb.x[1], 3u);
-            uint64_t m0 = 0, m1 = 0;
+            PSet m0, m1;
+            m0.clear();
+            m1.clear();
             if (gl < K) candidates_ap(i, X, m0, m1);
-            const int n0 = popc64(m0), n = n0 + popc64(m1);
+            const int n0 = m0.count(), n = n0 + m1.count();
             if (n > 0) {
                 int c = (int)below(pb.x[2], (uint32_t)n);
                 const int role = c >= n0;
                 if (role) c -= n0;
-                const int j = kth_bit(role ? m1 : m0, c);
+                const int j = (role ? m1 : m0).kth(c);  // one search, on the chosen set
                 desc = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)X << 16) |
                        ((uint32_t)role << 18);
                 const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
@@ -1343,7 +1410,7 @@ __global__ void __launch_bounds__(256) __attribute__((
                       lmax <= (int)(8 * sizeof(T)) && h->mode == (Z2 ? 1 : 0) &&
                       h->r_cap <= a.cap && h->rank >= 0 && h->rank <= h->r_cap &&
                       h->best_rank >= 0 && h->best_rank <= a.cap && h->start_rank >= 0 &&
-                      h->start_rank <= a.cap && (!AP || a.cap <= 64);
+                      h->start_rank <= a.cap && (!AP || a.cap <= 64 * S) && (!IX || a.cap <= 64);
     if (!sane || done != 0) {
         if (!sane && wk.gl == 0 && done == 0) h->done = -1;
         return;

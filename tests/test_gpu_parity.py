@@ -101,13 +101,32 @@ def test_indexed_strategy_small_mixed_formats_heavy_expand(ctx, lanes):
     assert cnt[:, 7].sum() > 0 and cnt[:, 6].sum() > 0  # expands and merges happened
 
 
-def test_mixed_formats_one_launch(ctx):
+@pytest.mark.parametrize("mode", [tsf.TSF_TERNARY, tsf.TSF_Z2])
+def test_mixed_formats_one_launch(ctx, mode):
+    """Capacity 88: term-parallel kernels, and attempt-parallel kernels with
+    two-word partner sets (terms 64.. in the second word)."""
     fmts = [(3, 3, 4), (3, 4, 5), (4, 4, 4), (4, 4, 5)]
-    groups = [(_std(*f), 12, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
+    groups = [(_std(*f, mode), 12, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
     prm = tsf.walk_params(base_seed=3, max_iters=2000, plateau=800, t_expand=1 << 27)
-    for lanes in (16, 32, 64):
-        b = _run(ctx, groups, prm, 2000, lanes=lanes)
-        compare(b, run_oracle(groups, prm, range(48), 2000), "mixed G=%d" % lanes)
+    ref = run_oracle(groups, prm, range(48), 2000)
+    for lanes, strategy in ((16, 2), (32, 2), (64, 2), (4, 1), (8, 1), (16, 1), (32, 1)):
+        b = _run(ctx, groups, prm, 2000, lanes=lanes, strategy=strategy)
+        compare(b, ref, "mixed mode=%d G=%d s=%d" % (mode, lanes, strategy))
+
+
+@pytest.mark.parametrize("fmt,cap", [((4, 4, 4), 80), ((2, 2, 17), 76)])
+def test_attempt_parallel_rank_crossing_64(ctx, fmt, cap):
+    """(4,4,4) from rank 64 (32-bit factors) and (2,2,17) from rank 68
+    (factors of 34 entries: 64-bit words), frequent expands: ranks move across
+    the word boundary of the two-word partner sets."""
+    groups = [(_std(*fmt), 24, cap, 0)]
+    prm = tsf.walk_params(base_seed=11, max_iters=3000, plateau=700, t_expand=1 << 30)
+    b = _run(ctx, groups, prm, 3000, lanes=8, strategy=1)
+    hdr = b.headers()
+    compare(b, run_oracle(groups, prm, range(24), 3000), "ap2 crossing %s" % (fmt,))
+    # every walk starts at its best rank, where an expand is allowed
+    assert hdr["counters"][:, 7].sum() > 0
+    assert (b.verify_device(which=0).cpu().numpy() == 0).all()
 
 
 @pytest.mark.parametrize("strategy", [1, 2, 3])
