@@ -725,9 +725,34 @@ struct Walker {
     }
 
     // ------------------------------------------------------------------ flip
+    // A chosen flip, packed: i | j << 10 | X << 20 | role << 22 (terms below
+    // 1024; kNoFlip: none)
+    static constexpr uint32_t kNoFlip = ~0u;
+    __device__ __forceinline__ static uint32_t pack_flip(int i, int j, int X, int role)
+    {
+        return (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)X << 20) | ((uint32_t)role << 22);
+    }
+    __device__ __forceinline__ void apply_packed(uint32_t d, int &fi, int &fj)
+    {
+        fi = d & 0x3FF;
+        fj = (d >> 10) & 0x3FF;
+        apply_flip(fi, fj, (d >> 20) & 3, (d >> 22) & 1, zfi, zfj);
+    }
+
+    // The searches (attempts, then the cyclic fallback) only choose the flip;
+    // it is applied at one point afterwards, so a wavefront whose walks took
+    // different searches applies their flips together.
     __device__ bool try_flip(int &fi, int &fj)
     {
         if (r < 2) return false;
+        const uint32_t pick = choose_flip();
+        if (pick == kNoFlip) return false;
+        apply_packed(pick, fi, fj);
+        return true;
+    }
+
+    __device__ uint32_t choose_flip()
+    {
         const int T_ = a->flip_tries;
         if constexpr (AP) {
             update_scan_end();
@@ -762,20 +787,14 @@ struct Walker {
                         const int role = c >= n0;
                         if (role) c -= n0;
                         const int j = (role ? m1 : m0).kth(c);  // one search, on the chosen set
-                        pick = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)X << 16) |
-                               ((uint32_t)role << 18);
+                        pick = pack_flip(i, j, X, role);
                     }
-                    pick = from_lane(pick, win);
-                    const int pi = pick & 0xFF, pj = (pick >> 8) & 0xFF;
                     cnt[C_ATTEMPTS] += (uint32_t)(base + win + 1);
-                    apply_flip(pi, pj, (pick >> 16) & 3, (pick >> 18) & 1, zfi, zfj);
-                    fi = pi;
-                    fj = pj;
-                    return true;
+                    return from_lane(pick, win);
                 }
             }
             cnt[C_ATTEMPTS] += (uint32_t)T_;
-            return fallback_ap(fi, fj);
+            return fallback_ap();
         } else {
             uint64_t m0[S], m1[S];
             int n0, n1;
@@ -792,13 +811,10 @@ struct Walker {
                     const int role = c >= n0;
                     if (role) c -= n0;
                     const int j = role ? select_tp(m1, c) : select_tp(m0, c);
-                    apply_flip(i, j, X, role, zfi, zfj);
-                    fi = i;
-                    fj = j;
-                    return true;
+                    return pack_flip(i, j, X, role);
                 }
             }
-            return fallback_tp(fi, fj);
+            return fallback_tp();
         }
     }
 
@@ -806,7 +822,7 @@ struct Walker {
     // pair p0 = U(w0, 3r); the pairs p = 3i + X are visited cyclically from p0
     // and the first pair with a valid partner yields candidate U(w1, n).
     // None at all: a dead end.
-    __device__ bool fallback_tp(int &fi, int &fj)
+    __device__ uint32_t fallback_tp()
     {
         cnt[C_FALLBACKS]++;
         uint64_t m0[S], m1[S];
@@ -825,17 +841,14 @@ struct Walker {
             const int role = c >= n0;
             if (role) c -= n0;
             const int j = role ? select_tp(m1, c) : select_tp(m0, c);
-            apply_flip(i, j, X, role, zfi, zfj);
-            fi = i;
-            fj = j;
-            return true;
+            return pack_flip(i, j, X, role);
         }
-        return false;
+        return kNoFlip;
     }
 
     // The same search with G consecutive pairs per round, one per lane; the
     // first lane (in pair order) with a partner wins.
-    __device__ bool fallback_ap(int &fi, int &fj)
+    __device__ uint32_t fallback_ap()
     {
         cnt[C_FALLBACKS]++;
         const Philox4 w = walk_block(seed, t, (uint32_t)a->flip_tries, 0);
@@ -860,18 +873,12 @@ struct Walker {
                     const int role = c >= n0;
                     if (role) c -= n0;
                     const int j = (role ? m1 : m0).kth(c);  // one search, on the chosen set
-                    packed = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)X << 16) |
-                             ((uint32_t)role << 18);
+                    packed = pack_flip(i, j, X, role);
                 }
-                packed = from_lane(packed, win);
-                const int pi = packed & 0xFF, pj = (packed >> 8) & 0xFF;
-                apply_flip(pi, pj, (packed >> 16) & 3, (packed >> 18) & 1, zfi, zfj);
-                fi = pi;
-                fj = pj;
-                return true;
+                return from_lane(packed, win);
             }
         }
-        return false;
+        return kNoFlip;
     }
 
     // ------------------------------------------------------------------ reduce
@@ -1347,23 +1354,19 @@ struct Walker {
         const uint64_t win_mask = gballot(valid && score == best);
         cnt[C_ATTEMPTS] += (uint32_t)K;
         int fi = -1, fj = -1;
-        bool found;
+        uint32_t d = kNoFlip;
         uint8_t choice = 255;
         if (win_mask) {
             const int win = __builtin_ctzll(win_mask);
-            const uint32_t d = from_lane(desc, win);
-            fi = d & 0xFF;
-            fj = (d >> 8) & 0xFF;
-            apply_flip(fi, fj, (d >> 16) & 3, (d >> 18) & 1, zfi, zfj);
-            found = true;
+            const uint32_t c = from_lane(desc, win);  // the candidate layout of propose()
+            d = pack_flip(c & 0xFF, (c >> 8) & 0xFF, (c >> 16) & 3, (c >> 18) & 1);
             choice = (uint8_t)win;
-        } else {
-            found = false;
-            if (r >= 2) {
-                update_scan_end();
-                found = fallback_ap(fi, fj);
-            }
+        } else if (r >= 2) {
+            update_scan_end();
+            d = fallback_ap();
         }
+        const bool found = d != kNoFlip;
+        if (found) apply_packed(d, fi, fj);
         if (a->choice && gl == 0 && t <= a->choice_cap)
             a->choice[(size_t)walk * a->choice_cap + (t - 1)] = choice;
         finish_iteration(found, fi, fj);
