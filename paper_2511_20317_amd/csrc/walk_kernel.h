@@ -574,10 +574,7 @@ struct Walker {
             wave_lds_sync();
             // a term with a zero factor is removed next, and its removal
             // clears its bit from every mask: only a survivor is refreshed
-            if (!zi)
-                refresh_one(i, Y, false);
-            else if (!zj)
-                refresh_one(j, Z, false);
+            if (!zi || !zj) refresh_one(!zi ? i : j, !zi ? Y : Z, false);
             return;
         }
         st(i, Y, ny);
@@ -993,30 +990,27 @@ struct Walker {
         // the partner is consumed
         if (qq == 0 && tr1 == k) tr1 = -1;
         if (qq == 1 && tr0 == k) tr0 = -1;
-        if (md.d == 0) {
-            if (qq == 0)
-                tr0 = -1;
-            else
-                tr1 = -1;
-            swap_remove(hi, tr0, tr1);
-            swap_remove(lo, tr0, tr1);
-            return;
+        const bool vanish = md.d == 0;
+        if (!vanish) {
+            TV<T> nt[3] = {kind == 0 ? md : tt[0], kind == 1 ? md : tt[1],
+                           kind == 2 ? md : tt[2]};
+            normalise_regs(nt);
+            store_term(lo, nt);
+            wave_lds_sync();
+            if constexpr (IX) {
+                // the merged factor is new at slot lo; the two shared factors
+                // are those of the term that held lo (w possibly negated,
+                // which the index ignores)
+                refresh_one(lo, kind, false);
+            }
         }
-        TV<T> nt[3] = {kind == 0 ? md : tt[0], kind == 1 ? md : tt[1], kind == 2 ? md : tt[2]};
-        normalise_regs(nt);
-        store_term(lo, nt);
-        wave_lds_sync();
-        if constexpr (IX) {
-            // the merged factor is new at slot lo; the two shared factors are
-            // those of the term that held lo (w possibly negated, which the
-            // index ignores)
-            refresh_one(lo, kind, false);
-        }
+        // the merged term keeps slot lo, or (a zero merged factor) both go
         if (qq == 0)
-            tr0 = lo;
+            tr0 = vanish ? -1 : lo;
         else
-            tr1 = lo;
+            tr1 = vanish ? -1 : lo;
         swap_remove(hi, tr0, tr1);
+        if (vanish) swap_remove(lo, tr0, tr1);
     }
 
     // Reduce the two terms modified by the flip, cascading: the first tracked
@@ -1042,18 +1036,25 @@ struct Walker {
             if (ib >= 0) load_term(ib, tb);
             int ka, kb;
             find_merges(ia, ta, ib, tb, ka, kb);
+            // the first tracked term merges while it has a partner, then the
+            // second (one merge_into call site)
+            int qq = -1, k = -1;
             if (!done0) {
                 if (ka >= 0) {
-                    ++merges;
-                    merge_into(0, ka, tr0, tr1);
-                    if (tr0 < 0) done0 = true;
-                    continue;
+                    qq = 0;
+                    k = ka;
+                } else {
+                    done0 = true;
                 }
-                done0 = true;
             }
-            if (ib < 0 || kb < 0) break;
+            if (qq < 0) {
+                if (ib < 0 || kb < 0) break;
+                qq = 1;
+                k = kb;
+            }
             ++merges;
-            merge_into(1, kb, tr0, tr1);
+            merge_into(qq, k, tr0, tr1);
+            if (qq == 0 && tr0 < 0) done0 = true;
         }
         return merges;
     }
@@ -1195,78 +1196,68 @@ struct Walker {
     // everything of Algorithm 1 after try_flip
     __device__ void finish_iteration(bool found, int fi, int fj)
     {
+        // each costly step (best copy, removal, expand, restart) has one call
+        // site, so that the walks of a wavefront that take it do so together
+        bool improved = false, accepted = false, grow = false;
         if (!found) {
             // Algorithm 1: no flip -> expand, continue (the additions
             // objective keeps the rank and does not expand)
             cnt[C_DEAD_ENDS]++;
-            if (!additions) expand();
-            restart_check();
-            write_log(false);
-            return;
-        }
-        cnt[C_FLIPS]++;
-        if (additions) {
-            // the rank is unchanged: best by non-zero count, no reduce or expand
+            grow = !additions;
+        } else {
+            cnt[C_FLIPS]++;
+            int tr0 = fi, tr1 = fj;
+            // gates: block (t, 0, 1), drawn by the last lane of the group
             const uint32_t g0 = from_lane(pb.x[0], G - 1);
-            if (nnz < best_nnz) {
-                store_scheme(a->best + (size_t)walk * a->cap * 6);
-                best_nnz = nnz;
+            if (additions) {
+                // the rank is unchanged: best by non-zero count, no reduce or
+                // expand
+                improved = nnz < best_nnz;
+                accepted = !improved && nnz == best_nnz && (uint64_t)g0 < a->t_eq;
+            } else {
+                // terms with a zero factor go, the higher index first
+                const bool zi = zfi, zj = zfj;
+                const int h1 = zi && zj ? (fi > fj ? fi : fj) : (zi ? fi : (zj ? fj : -1));
+                const int h2 = zi && zj ? (fi > fj ? fj : fi) : -1;
+                if (h1 >= 0) {
+                    swap_remove(h1, tr0, tr1);
+                    cnt[C_ZERO_REMOVED]++;
+                }
+                if (h2 >= 0) {
+                    swap_remove(h2, tr0, tr1);
+                    cnt[C_ZERO_REMOVED]++;
+                }
+                improved = r < best_rank;
+                accepted = !improved && r == best_rank && (uint64_t)g0 < a->t_eq;
+            }
+            if (improved || accepted) {
+                const int c = store_scheme(a->best + (size_t)walk * a->cap * 6);
+                best_nnz = additions ? nnz : c;
                 best_rank = r;
+            }
+            if (improved) {
                 plateau_start = t;
                 if (gl == 0 && n_rec < a->rec_cap) {
                     tsf_record *rc = a->rec + (size_t)walk * a->rec_cap + n_rec;
                     rc->iter = t;
-                    rc->rank = nnz - 2 * r - mp;
+                    rc->rank = additions ? nnz - 2 * r - mp : r;
                     rc->reserved = 0;
                 }
                 n_rec++;
                 cnt[C_IMPROVEMENTS]++;
-            } else if (nnz == best_nnz && (uint64_t)g0 < a->t_eq) {
-                store_scheme(a->best + (size_t)walk * a->cap * 6);
-                best_rank = r;
+            } else if (accepted) {
                 cnt[C_EQ_ACCEPTS]++;
             }
-            restart_check();
-            write_log(true);
-            return;
-        }
-        int tr0 = fi, tr1 = fj;
-        const bool zi = zfi, zj = zfj;
-        if (zi && zj) {
-            swap_remove(fi > fj ? fi : fj, tr0, tr1);
-            swap_remove(fi > fj ? fj : fi, tr0, tr1);
-            cnt[C_ZERO_REMOVED] += 2;
-        } else if (zi) {
-            swap_remove(fi, tr0, tr1);
-            cnt[C_ZERO_REMOVED]++;
-        } else if (zj) {
-            swap_remove(fj, tr0, tr1);
-            cnt[C_ZERO_REMOVED]++;
-        }
-        // gates: block (t, 0, 1), drawn by the last lane of the group
-        const uint32_t g0 = from_lane(pb.x[0], G - 1);
-        const uint32_t g1 = from_lane(pb.x[1], G - 1);
-        const uint32_t g2 = from_lane(pb.x[2], G - 1);
-        if (r < best_rank) {
-            best_nnz = store_scheme(a->best + (size_t)walk * a->cap * 6);
-            best_rank = r;
-            plateau_start = t;
-            if (gl == 0 && n_rec < a->rec_cap) {
-                tsf_record *rc = a->rec + (size_t)walk * a->rec_cap + n_rec;
-                rc->iter = t;
-                rc->rank = r;
-                rc->reserved = 0;
+            if (!additions) {
+                const uint32_t g1 = from_lane(pb.x[1], G - 1);
+                const uint32_t g2 = from_lane(pb.x[2], G - 1);
+                if ((uint64_t)g1 < a->t_reduce) cnt[C_MERGES] += (uint32_t)reduce(tr0, tr1);
+                grow = (uint64_t)g2 < a->t_expand && r <= best_rank + 2 && r < r_cap;
             }
-            n_rec++;
-            cnt[C_IMPROVEMENTS]++;
-        } else if (r == best_rank && (uint64_t)g0 < a->t_eq) {
-            best_nnz = store_scheme(a->best + (size_t)walk * a->cap * 6);
-            cnt[C_EQ_ACCEPTS]++;
         }
-        if ((uint64_t)g1 < a->t_reduce) cnt[C_MERGES] += (uint32_t)reduce(tr0, tr1);
-        if ((uint64_t)g2 < a->t_expand && r <= best_rank + 2 && r < r_cap) expand();
+        if (grow) expand();
         restart_check();
-        write_log(true);
+        write_log(found);
     }
 
     __device__ void write_log(bool flipped)
