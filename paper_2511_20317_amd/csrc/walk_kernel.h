@@ -119,10 +119,13 @@ struct TV {
     T d, s;
 };
 
+// (the comparisons below use & and | rather than && and ||: both words are
+// in registers already, and short-circuit forms compile to branches that can
+// delay or split the LDS reads feeding them)
 template <typename T>
 __device__ __forceinline__ bool eqv(TV<T> a, TV<T> b)
 {
-    return a.d == b.d && a.s == b.s;
+    return (a.d == b.d) & (a.s == b.s);
 }
 
 // Order LDS accesses of the lanes of one wavefront: LDS instructions of a
@@ -295,9 +298,8 @@ struct Walker {
     // relation of the match index
     __device__ __forceinline__ static bool equiv(TV<T> x, TV<T> y, int X)
     {
-        if (x.d != y.d) return false;
-        if constexpr (Z2) return true;
-        return x.s == y.s || (X == 2 && (x.s ^ x.d) == y.s);
+        if constexpr (Z2) return x.d == y.d;
+        return (x.d == y.d) & ((x.s == y.s) | ((X == 2) & ((x.s ^ x.d) == y.s)));
     }
 
     // largest rank of the walks of this wavefront (a wave-uniform loop bound)
