@@ -227,6 +227,9 @@ struct Walker {
     int64_t walk;
     // this iteration's Philox block of this lane (attempt gl, or the gate)
     Philox4 pb;
+    // the gate words (block (t, 0, 1), drawn by lane G-1), broadcast to the
+    // group as soon as they are drawn
+    uint32_t gate[3];
     // zero-factor flags of the two terms of the last flip
     bool zfi, zfj;
     // this iteration is written to the training log
@@ -526,10 +529,13 @@ struct Walker {
     {
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
         const int Y = role ? B : A, Z = role ? A : B;
-        const int sg = rel(ld(i, X), ld(j, X), X);
+        // every factor the flip reads is read up front (one round of reads)
+        const TV<T> xi = ld(i, X), yi = ld(i, Y), zi0 = ld(i, Z);
+        const TV<T> xj = ld(j, X), yj = ld(j, Y), zj0 = ld(j, Z);
+        const int sg = rel(xi, xj, X);
         if (logging && gl == 0) {
             tsf_flip_log *lg = a->log + (size_t)walk * a->log_cap + (t - 1);
-            const TV<T> fv[6] = {ld(i, X), ld(i, Y), ld(i, Z), ld(j, X), ld(j, Y), ld(j, Z)};
+            const TV<T> fv[6] = {xi, yi, zi0, xj, yj, zj0};
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 lg->f[2 * q] = (uint64_t)fv[q].d;
@@ -538,9 +544,8 @@ struct Walker {
             lg->rank_before = r;
         }
         TV<T> ny, nz;
-        const TV<T> yi = ld(i, Y), zj0 = ld(j, Z);
-        axpy(sg, yi, ld(j, Y), ny);
-        axpy(-1, zj0, ld(i, Z), nz);
+        axpy(sg, yi, yj, ny);
+        axpy(-1, zj0, zi0, nz);
         zi = ny.d == 0;
         zj = nz.d == 0;
         if (additions)
@@ -548,16 +553,17 @@ struct Walker {
                    popc64((uint64_t)zj0.d);
         if constexpr (!Z2) {
             // Sec. 3.6: a u or v factor whose first non-zero entry is -1 is
-            // negated, and w absorbs the sign
+            // negated, and w absorbs the sign (w of term i is x_i or z_i when
+            // y is not w; w of term j is x_j or y_j when z is not w)
             if (Y != 2 && (ny.s & ny.d & (~ny.d + 1))) {
                 ny.s ^= ny.d;
-                TV<T> w = ld(i, 2);
+                TV<T> w = X == 2 ? xi : zi0;
                 w.s ^= w.d;
                 st(i, 2, w);
             }
             if (Z != 2 && (nz.s & nz.d & (~nz.d + 1))) {
                 nz.s ^= nz.d;
-                TV<T> w = ld(j, 2);
+                TV<T> w = X == 2 ? xj : yj;
                 w.s ^= w.d;
                 st(j, 2, w);
             }
@@ -1192,6 +1198,8 @@ struct Walker {
         // this iteration's draws: lane q < G-1 -> flip attempt q, lane G-1 -> gates
         const bool gate_lane = gl == G - 1;
         pb = walk_block(seed, t, gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gate[q] = from_lane(pb.x[q], G - 1);
         logging = a->log != nullptr && t <= a->log_cap;
     }
 
@@ -1210,7 +1218,7 @@ struct Walker {
             cnt[C_FLIPS]++;
             int tr0 = fi, tr1 = fj;
             // gates: block (t, 0, 1), drawn by the last lane of the group
-            const uint32_t g0 = from_lane(pb.x[0], G - 1);
+            const uint32_t g0 = gate[0];
             if (additions) {
                 // the rank is unchanged: best by non-zero count, no reduce or
                 // expand
@@ -1251,8 +1259,8 @@ struct Walker {
                 cnt[C_EQ_ACCEPTS]++;
             }
             if (!additions) {
-                const uint32_t g1 = from_lane(pb.x[1], G - 1);
-                const uint32_t g2 = from_lane(pb.x[2], G - 1);
+                const uint32_t g1 = gate[1];
+                const uint32_t g2 = gate[2];
                 if ((uint64_t)g1 < a->t_reduce) cnt[C_MERGES] += (uint32_t)reduce(tr0, tr1);
                 grow = (uint64_t)g2 < a->t_expand && r <= best_rank + 2 && r < r_cap;
             }
