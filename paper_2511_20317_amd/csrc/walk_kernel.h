@@ -34,9 +34,14 @@
 //    kept in LDS next to the terms -- for every term k and factor kind X a
 //    64-bit mask of the other live terms whose factor X equals that of k (w
 //    up to sign).  A flip changes two factors, so the index is refreshed in
-//    two lane-parallel passes over the terms, and both the partner scan of
-//    an attempt and the two-shared-factors search of a reduction become mask
+//    one lane-parallel pass over the terms, and both the partner scan of an
+//    attempt and the two-shared-factors search of a reduction become mask
 //    lookups.
+//
+// The searches only choose a flip; one call site applies it.  Every costly
+// step of an iteration (apply, removal, best copy, merge, expand, restart)
+// has a single call site, so the walks of a wavefront that take a step in the
+// same iteration take it in one pass.
 #pragma once
 #include <hip/hip_runtime.h>
 
