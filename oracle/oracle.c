@@ -922,11 +922,12 @@ static int fallback_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, i
  * sampled): attempt a = 0..flip_tries-1 draws block (t,a,0): term
  * i = U(w0, r), factor X = U(w1, 3); its candidates are the valid
  * (j, role) in order role 0 then 1, j ascending; a non-empty list yields
- * candidate U(w2, |list|).  If every attempt is empty, block (t, flip_tries, 0)
- * gives a starting pair p0 = U(w0, 3r); the pairs p = 3i + X are visited
- * cyclically from p0 and the first one with candidates yields candidate
- * U(w1, |list|).  Only when no pair has a candidate (no valid flip exists at
- * all) does try_flip fail.  On success *pi and *pj hold the modified terms. */
+ * candidate U(w2, |list|).  If every attempt is empty, the unused fourth
+ * words of blocks (t,0,0) and (t,1,0) give a starting pair p0 = U(w3, 3r)
+ * (block (t,0,0)); the pairs p = 3i + X are visited cyclically from p0 and the
+ * first one with candidates yields candidate U(w3, |list|) (block (t,1,0)).
+ * Only when no pair has a candidate (no valid flip exists at all) does
+ * try_flip fail.  On success *pi and *pj hold the modified terms. */
 static int try_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, int *pj, int *pX,
                     int *prole)
 {
@@ -957,19 +958,20 @@ static int fallback_flip(or_walk *w, const or_params *prm, int64_t t, int *pi, i
 {
     or_scheme *s = &w->cur;
     int r = s->r;
-    uint32_t rw[4];
+    uint32_t b0[4], b1[4];
     int j = -1, sg = 0, role = 0;
     const int keep = prm->objective == 1;
     w->c.fallbacks++;
-    draw(prm->seed, t, (uint32_t)prm->flip_tries, 0, rw);
+    draw(prm->seed, t, 0, 0, b0);
+    draw(prm->seed, t, 1, 0, b1);
     int npairs = 3 * r;
-    int p0 = uniform_below(rw[0], npairs);
+    int p0 = uniform_below(b0[3], npairs);
     for (int q = 0; q < npairs; ++q) {
         int p = (p0 + q) % npairs;
         int i = p / 3, X = p % 3;
         int n = attempt_candidates(s, i, X, keep, -1, &j, &sg, &role);
         if (n == 0) continue;
-        attempt_candidates(s, i, X, keep, uniform_below(rw[1], n), &j, &sg, &role);
+        attempt_candidates(s, i, X, keep, uniform_below(b1[3], n), &j, &sg, &role);
         *pi = i; *pj = j; *pX = X; *prole = role;
         return 1;
     }

@@ -828,18 +828,19 @@ struct Walker {
         }
     }
 
-    // When every attempt failed: block (t, flip_tries, 0) gives a starting
-    // pair p0 = U(w0, 3r); the pairs p = 3i + X are visited cyclically from p0
-    // and the first pair with a valid partner yields candidate U(w1, n).
-    // None at all: a dead end.
+    // When every attempt failed: the unused fourth words of the blocks of
+    // attempts 0 and 1 (drawn by lanes 0 and 1 of the group) give a starting
+    // pair p0 = U(w3 of (t,0,0), 3r); the pairs p = 3i + X are visited
+    // cyclically from p0 and the first pair with a valid partner yields
+    // candidate U(w3 of (t,1,0), n).  None at all: a dead end.
     __device__ uint32_t fallback_tp()
     {
         cnt[C_FALLBACKS]++;
         uint64_t m0[S], m1[S];
         int n0, n1;
-        const Philox4 w = walk_block(seed, t, (uint32_t)a->flip_tries, 0);
+        const uint32_t f0 = from_lane(pb.x[3], 0), f1 = from_lane(pb.x[3], 1);
         const int npairs = 3 * r;
-        const int p0 = (int)below(w.x[0], (uint32_t)npairs);
+        const int p0 = (int)below(f0, (uint32_t)npairs);
         for (int q = 0; q < npairs; ++q) {
             int p = p0 + q;
             if (p >= npairs) p -= npairs;
@@ -847,7 +848,7 @@ struct Walker {
             candidates_tp(i, X, m0, m1, n0, n1);
             const int n = n0 + n1;
             if (n == 0) continue;
-            int c = (int)below(w.x[1], (uint32_t)n);
+            int c = (int)below(f1, (uint32_t)n);
             const int role = c >= n0;
             if (role) c -= n0;
             const int j = role ? select_tp(m1, c) : select_tp(m0, c);
@@ -861,9 +862,9 @@ struct Walker {
     __device__ uint32_t fallback_ap()
     {
         cnt[C_FALLBACKS]++;
-        const Philox4 w = walk_block(seed, t, (uint32_t)a->flip_tries, 0);
+        const uint32_t f0 = from_lane(pb.x[3], 0), f1 = from_lane(pb.x[3], 1);
         const int npairs = 3 * r;
-        const int p0 = (int)below(w.x[0], (uint32_t)npairs);
+        const int p0 = (int)below(f0, (uint32_t)npairs);
         for (int base = 0; base < npairs; base += G) {
             const int q = base + gl;
             int p = p0 + q;
@@ -879,7 +880,7 @@ struct Walker {
                 const int win = __builtin_ctzll(ok);
                 uint32_t packed = 0;
                 if (gl == win) {
-                    int c = (int)below(w.x[1], (uint32_t)n);
+                    int c = (int)below(f1, (uint32_t)n);
                     const int role = c >= n0;
                     if (role) c -= n0;
                     const int j = (role ? m1 : m0).kth(c);  // one search, on the chosen set

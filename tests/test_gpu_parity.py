@@ -305,13 +305,17 @@ def test_autotune_leaves_state_and_keeps_parity(ctx):
 # ------------------------------------------------------- additions objective
 def _oracle_rank_scheme(fmt, target, seed, z2=False):
     """A scheme of the given rank found by the oracle's own rank walk (no GPU
-    output is an input of these tests)."""
+    output is an input of these tests): the first walk seed from `seed` on
+    whose walk reaches the rank."""
     from oracle import pyoracle as O
     m, n, p = fmt
-    prm = O.make_params(seed=seed, max_iters=300000, plateau=30000, target_rank=target,
-                        r0=m * n * p)
-    w = O.new_walk(O.standard(m, n, p, z2=z2))
-    O.run(w, prm, 300000)
+    for sd in range(seed, seed + 16):
+        prm = O.make_params(seed=sd, max_iters=300000, plateau=30000, target_rank=target,
+                            r0=m * n * p)
+        w = O.new_walk(O.standard(m, n, p, z2=z2))
+        O.run(w, prm, 300000)
+        if w.best_rank == target:
+            break
     assert w.best_rank == target
     d = O.from_c(w.best)
     return tsf.Scheme(m, n, p, d["U"], d["V"], d["W"], mode=tsf.TSF_Z2 if z2 else tsf.TSF_TERNARY)
