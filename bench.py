@@ -104,17 +104,23 @@ def learned_vs_uniform(ctx, args):
     net.set_params(rng.standard_normal((512, 256)) * np.sqrt(2 / 64), np.zeros(256),
                    rng.standard_normal((256, 256)) * np.sqrt(2 / 256), np.zeros(256),
                    rng.standard_normal(256) * np.sqrt(1 / 256), np.zeros(1))
-    ev0 = learn.evaluate(net, rec, idx, lab)
+    # held-out flips: walks of another seed block
+    held, hidx, hlab = learn.collect(ctx, s333, max(args.learn_walks // 4, 1), args.learn_iters,
+                                     35, base_seed=2 * 10 ** 7)
+    ev0 = learn.evaluate(net, held, hidx, hlab)
     t0 = time.perf_counter()
     hist = learn.train(net, rec, idx, lab, args.learn_steps, batch=4096, lr=1e-3,
                        log_every=max(args.learn_steps // 5, 1))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    ev = learn.evaluate(net, rec, idx, lab)
-    del rec
+    ev = learn.evaluate(net, held, hidx, hlab)
+    p = float(hlab.mean())
+    constant_loss = -(p * np.log(p) + (1 - p) * np.log(1 - p)) if 0 < p < 1 else 0.0
+    del rec, held
     out = {"train": {"logged_iterations": int(idx.size), "positive_rate": float(lab.mean()),
                      "collect_s": t_collect, "train_s": t_train, "steps": args.learn_steps,
-                     "batch": 4096, "loss_history": hist, "eval_before": ev0, "eval_after": ev}}
+                     "batch": 4096, "loss_history": hist, "held_out_before": ev0,
+                     "held_out_after": ev, "constant_predictor_loss": constant_loss}}
     results = {}
     for fmt, r_cap, ladder in [((3, 3, 3), 35, (26, 25, 24, 23)), ((4, 4, 4), 64, (63, 62, 61, 60))]:
         s = tsf.init_scheme(*fmt)

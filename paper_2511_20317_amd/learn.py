@@ -124,7 +124,7 @@ def time_to_ranks(ctx, scheme, n_walks, r_cap, ladder, wall_s, base_seed, net=No
     ws = tsf.LearnWorkspace(n_walks) if net is not None else None
     best_col = b.hdr.view(torch.int32).view(n_walks, 40)[:, 7]
     iters_per_call = iters_per_call or (20 if net is not None else 2000)
-    hit_s, hit_it = {}, {}
+    hit_s = {}
     done_iters = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -139,10 +139,21 @@ def time_to_ranks(ctx, scheme, n_walks, r_cap, ladder, wall_s, base_seed, net=No
         for rank in ladder:
             if best <= rank and rank not in hit_s:
                 hit_s[rank] = now
-                hit_it[rank] = done_iters
         if now >= wall_s or best <= min(ladder):
             break
     hdr = b.headers()
+    # the exact first iteration of each rung, from the walks' improvement
+    # records (iteration, rank): independent of the call granularity
+    rec = b.rec.cpu().numpy()
+    n_rec = np.minimum(hdr["n_rec"], b.rec_cap)
+    first_it = {}
+    for w in range(n_walks):
+        its = rec[w, :n_rec[w], 0]
+        rks = rec[w, :n_rec[w], 1] & 0xFFFFFFFF
+        for rank in ladder:
+            hit = its[rks <= rank]
+            if hit.size and (rank not in first_it or hit.min() < first_it[rank]):
+                first_it[rank] = int(hit.min())
     return {"wall_s": now, "iterations": done_iters, "time_to_rank_s": hit_s,
-            "iters_to_rank": hit_it, "flips": int(hdr["counters"][:, 1].sum()),
+            "iters_to_rank": first_it, "flips": int(hdr["counters"][:, 1].sum()),
             "best_rank": int(hdr["best_rank"].min())}
