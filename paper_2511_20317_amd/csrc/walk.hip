@@ -790,7 +790,8 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     // of 4 for the indexed strategy, which reads four terms at a time)
     const int cap2 = ix ? (b->capacity + 3) & ~3 : b->capacity + (b->capacity & 1);
     // per walk: the terms, and for the indexed strategy 3 match masks per term
-    const size_t per_walk = (size_t)cap2 * 6 * word + (ix ? (size_t)cap2 * 3 * 8 : 0);
+    // (rows of `capacity` masks, not padded)
+    const size_t per_walk = (size_t)cap2 * 6 * word + (ix ? (size_t)b->capacity * 3 * 8 : 0);
     L.lds = (size_t)wpb * walks_per_wave * per_walk;
     if (L.lds > 160 * 1024)
         return tsf_fail(TSF_E_CAPACITY, "%zu bytes of LDS per workgroup exceed 160 KiB", L.lds);
@@ -812,6 +813,7 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     a.mode = b->mode;
     a.max_len = b->max_len;
     a.cap2 = cap2;
+    a.capm = b->capacity;
     a.log = b->log;
     a.log_cap = b->log ? b->log_cap : 0;
     a.hdr = b->hdr;

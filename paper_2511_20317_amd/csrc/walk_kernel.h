@@ -31,9 +31,9 @@
 //    lanes split the terms (slot q of lane l is term q*G + l), with one group
 //    ballot per slot and role;
 //  * indexed attempt-parallel (IX, at most 64 terms): AP over a match index
-//    kept in LDS next to the terms -- for every term k and factor kind X a
-//    64-bit mask of the other live terms whose factor X equals that of k (w
-//    up to sign).  A flip changes two factors, so the index is refreshed in
+//    kept in LDS after the terms of the workgroup -- for every term k and
+//    factor kind X a 64-bit mask of the other live terms whose factor X
+//    equals that of k (w up to sign).  A flip changes two factors, so the index is refreshed in
 //    one lane-parallel pass over the terms, and both the partner scan of an
 //    attempt and the two-shared-factors search of a reduction become mask
 //    lookups.
@@ -66,6 +66,7 @@ struct KArgs {
     int32_t mode;
     int32_t max_len;
     int32_t cap2;  // LDS stride per factor kind: cap rounded up to even (IX: to 4)
+    int32_t capm;  // IX: row stride of the match masks (the capacity)
     tsf_walk_header *hdr;
     uint64_t *cur;
     uint64_t *best;
@@ -218,7 +219,8 @@ struct Walker {
     int gshift;  // first lane of the group within the wavefront
     int cap2;
     T *lds;
-    uint64_t *mk;  // IX: match masks, mk[X*cap2 + k]
+    uint64_t *mk;  // IX: match masks, mk[X*capm + k]
+    int capm;      // IX: row stride of the masks (the capacity)
     // walk scalars, identical in every lane of the group
     uint64_t seed;
     int r, r_cap, best_rank, start_rank, target, n_rec;
@@ -320,7 +322,7 @@ struct Walker {
     }
 
     // ------------------------------------------------------------ index (IX)
-    // mk[X*cap2 + k], k < r: bit j set iff j != k, j < r and equiv(factor X
+    // mk[X*capm + k], k < r: bit j set iff j != k, j < r and equiv(factor X
     // of j, factor X of k).  Built from scratch after a scheme is loaded.
     __device__ void build_index()
     {
@@ -331,7 +333,7 @@ struct Walker {
                 uint64_t m = 0;
                 for (int j = 0; j < r; ++j)
                     m |= (j != k && equiv(ld(j, X), xk, X)) ? (1ull << j) : 0ull;
-                mk[X * cap2 + k] = m;
+                mk[X * capm + k] = m;
             }
         }
         wave_lds_sync();
@@ -389,13 +391,13 @@ struct Walker {
                 c2 = ((c2 & live & ~self2) ^ (uint32_t)(o2 >> jb)) & 0xFu;
                 for (; c1; c1 &= c1 - 1) {
                     const int j = jb + __builtin_ctz(c1);
-                    lds_xor(mk + X1 * cap2 + j, 1ull << k1);
-                    lds_xor(mk + X1 * cap2 + k1, 1ull << j);
+                    lds_xor(mk + X1 * capm + j, 1ull << k1);
+                    lds_xor(mk + X1 * capm + k1, 1ull << j);
                 }
                 for (; c2; c2 &= c2 - 1) {
                     const int j = jb + __builtin_ctz(c2);
-                    lds_xor(mk + X2 * cap2 + j, 1ull << k2);
-                    lds_xor(mk + X2 * cap2 + k2, 1ull << j);
+                    lds_xor(mk + X2 * capm + j, 1ull << k2);
+                    lds_xor(mk + X2 * capm + k2, 1ull << j);
                 }
             }
         }
@@ -407,17 +409,17 @@ struct Walker {
     __device__ void refresh_one(int k, int X, bool fresh)
     {
         const TV<T> nk = ld(k, X);
-        const uint64_t o = fresh ? 0ull : mk[X * cap2 + k];
+        const uint64_t o = fresh ? 0ull : mk[X * capm + k];
         if (fresh) {
-            if (gl == 0) mk[X * cap2 + k] = 0;
+            if (gl == 0) mk[X * capm + k] = 0;
             wave_lds_sync();
         }
 #pragma unroll 1
         for (int j = gl; j < r; j += G) {
             const bool e = j != k && equiv(ld(j, X), nk, X);
             if (e != (((o >> j) & 1ull) != 0)) {
-                lds_xor(mk + X * cap2 + j, 1ull << k);
-                lds_xor(mk + X * cap2 + k, 1ull << j);
+                lds_xor(mk + X * capm + j, 1ull << k);
+                lds_xor(mk + X * capm + k, 1ull << j);
             }
         }
         wave_lds_sync();
@@ -470,9 +472,9 @@ struct Walker {
                     const int dst = j == last ? h : j;
 #pragma unroll
                     for (int X = 0; X < 3; ++X) {
-                        uint64_t m = mk[X * cap2 + j] & ~bh;
+                        uint64_t m = mk[X * capm + j] & ~bh;
                         if (m & bl) m = (m & ~bl) | bh;
-                        mk[X * cap2 + dst] = m;
+                        mk[X * capm + dst] = m;
                     }
                 }
             }
@@ -574,7 +576,7 @@ struct Walker {
             }
         }
         if constexpr (IX) {
-            const uint64_t oy = mk[Y * cap2 + i], oz = mk[Z * cap2 + j];
+            const uint64_t oy = mk[Y * capm + i], oz = mk[Z * capm + j];
             st(i, Y, ny);
             st(j, Z, nz);
             if (!zi && !zj) {
@@ -684,7 +686,7 @@ struct Walker {
         const TV<T> xi = ld(i, X);
         PSet match;
         if constexpr (IX) {
-            match.w[0] = mk[X * cap2 + i];
+            match.w[0] = mk[X * capm + i];
         } else {
             const T nsi = (!Z2 && X == 2) ? (xi.s ^ xi.d) : xi.s;  // accepted signs besides xi.s
             const T *col = lds + idx(0, X);
@@ -975,7 +977,7 @@ struct Walker {
     // set, or -1
     __device__ __forceinline__ uint64_t two_shared(int ti) const
     {
-        const uint64_t mu = mk[ti], mv = mk[cap2 + ti], mw = mk[2 * cap2 + ti];
+        const uint64_t mu = mk[ti], mv = mk[capm + ti], mw = mk[2 * capm + ti];
         return (mu & mv) | (mu & mw) | (mv & mw);
     }
     __device__ int first_merge(uint64_t c, const TV<T> (&tt)[3]) const
@@ -1405,10 +1407,15 @@ __global__ void __launch_bounds__(256) __attribute__((
     wk.gl = lane % G;
     wk.gshift = grp * G;
     wk.cap2 = a.cap2;
-    // per walk: the terms (6*cap2 words), then for IX the masks (3*cap2 u64)
-    const size_t stride = (size_t)a.cap2 * 6 + (IX ? (size_t)a.cap2 * 3 * (8 / sizeof(T)) : 0);
-    wk.lds = smem + (size_t)(wave * W + grp) * stride;
-    wk.mk = reinterpret_cast<uint64_t *>(wk.lds + (size_t)a.cap2 * 6);
+    wk.capm = a.capm;
+    // the terms of every walk of the workgroup (6*cap2 words each), then for
+    // IX the masks of every walk (3*capm u64 each); the masks are not padded
+    // like the term rows, which keeps a wavefront's LDS small enough for one
+    // more wavefront per CU at (3,3,3)
+    const int slot = wave * W + grp;
+    wk.lds = smem + (size_t)slot * a.cap2 * 6;
+    wk.mk = reinterpret_cast<uint64_t *>(smem + (size_t)wpb * W * a.cap2 * 6) +
+            (size_t)slot * a.capm * 3;
     wk.a = &a;
     wk.walk = walk;
     tsf_walk_header *h = a.hdr + walk;
