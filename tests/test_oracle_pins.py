@@ -392,3 +392,91 @@ def test_round_split_invariance(fmt, expand):
     assert a.t == 6000 and a.c.restarts > 0
     if expand:
         assert a.c.expands > 0
+
+
+# ---------------------------------------------------------- flip sampling
+def _numpy_candidates(F, i, X):
+    """Valid partners (j, role) of attempt (term i, kind X), written from the
+    flip of Sec. 3.3.1 in numpy: x_j = s x_i (s = -1 only for w), then
+    y_i + s y_j and z_j - z_i must stay in {-1, 0, 1}; (Y, Z) are the other
+    kinds in u < v < w order, swapped for role 1; role 0 first, j ascending."""
+    A = 1 if X == 0 else 0
+    B = 1 if X == 2 else 2
+    out = []
+    for role in (0, 1):
+        Y, Z = (A, B) if role == 0 else (B, A)
+        for j in range(F[0].shape[0]):
+            if j == i:
+                continue
+            if np.array_equal(F[X][j], F[X][i]):
+                s = 1
+            elif X == 2 and np.array_equal(F[X][j], -F[X][i]):
+                s = -1
+            else:
+                continue
+            ny = F[Y][i] + s * F[Y][j]
+            nz = F[Z][j] - F[Z][i]
+            if np.abs(ny).max() <= 1 and np.abs(nz).max() <= 1:
+                out.append((j, role, Y, Z))
+    return out
+
+
+def _bits(v):
+    d = sum(1 << e for e, x in enumerate(v) if x != 0)
+    s = sum(1 << e for e, x in enumerate(v) if x < 0)
+    return d, s
+
+
+@pytest.mark.parametrize("flip_tries", [1, 7])
+def test_flip_sampling_reading(flip_tries):
+    """The flip each oracle iteration applies is the one the sampling reading
+    predicts from the Philox words alone: attempt a uses block (t, a, 0), term
+    U(w0, r), kind U(w1, 3), candidate U(w2, n) of the first attempt with
+    candidates; when none has one, the cyclic search starts at pair
+    U(w3 of (t,0,0), 3r) and picks U(w3 of (t,1,0), n).  The candidate lists
+    come from the independent numpy enumeration above; one attempt
+    (flip_tries 1) makes the fallback frequent."""
+    M32 = 0xFFFFFFFF
+    fallbacks = 0
+    for k in range(4):
+        seed = 4242 + k
+        prm = O.make_params(seed=seed, max_iters=10 ** 6, plateau=10 ** 6, r0=27,
+                            flip_tries=flip_tries)
+        w = O.new_walk(O.standard(3, 3, 3))
+        O.run(w, prm, 150 + 61 * k)
+        key = (seed & M32, seed >> 32)
+        for _ in range(40):
+            d = O.from_c(w.cur)
+            F = [d["U"].astype(np.int64), d["V"].astype(np.int64), d["W"].astype(np.int64)]
+            r = F[0].shape[0]
+            t = w.t + 1
+            pred = None
+            for a in range(flip_tries):
+                w0, w1, w2, _ = O.philox((t & M32, t >> 32, a, 0), key)
+                i, X = (w0 * r) >> 32, (w1 * 3) >> 32
+                c = _numpy_candidates(F, i, X)
+                if c:
+                    pred = (i, X) + c[(w2 * len(c)) >> 32]
+                    break
+            if pred is None:
+                fallbacks += 1
+                f0 = O.philox((t & M32, t >> 32, 0, 0), key)[3]
+                f1 = O.philox((t & M32, t >> 32, 1, 0), key)[3]
+                p0 = (f0 * 3 * r) >> 32
+                for q in range(3 * r):
+                    i, X = divmod((p0 + q) % (3 * r), 3)
+                    c = _numpy_candidates(F, i, X)
+                    if c:
+                        pred = (i, X) + c[(f1 * len(c)) >> 32]
+                        break
+            assert pred is not None  # (3,3,3) walks from the standard scheme never dead-end here
+            i, X, j, role, Y, Z = pred
+            logs = O.run_logged(w, prm, 1, t, 0)
+            lg = logs[t - 1]
+            assert lg.rank_before == r
+            want = [_bits(F[X][i]), _bits(F[Y][i]), _bits(F[Z][i]),
+                    _bits(F[X][j]), _bits(F[Y][j]), _bits(F[Z][j])]
+            got = [(lg.f[2 * q], lg.f[2 * q + 1]) for q in range(6)]
+            assert got == want, (seed, t, pred)
+    if flip_tries == 1:
+        assert fallbacks > 10
