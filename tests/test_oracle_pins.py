@@ -480,3 +480,90 @@ def test_flip_sampling_reading(flip_tries):
             assert got == want, (seed, t, pred)
     if flip_tries == 1:
         assert fallbacks > 10
+
+
+# ------------------------------------------------------------------ expand
+def _numpy_normalise(u, v, w):
+    """Sec. 3.6 on one term: the first non-zero of u, then of v, made
+    positive; w absorbs each sign change."""
+    u, v, w = u.copy(), v.copy(), w.copy()
+    for x in (u, v):
+        nz = np.flatnonzero(x)
+        if nz.size and x[nz[0]] < 0:
+            x *= -1
+            w *= -1
+    return u, v, w
+
+
+def _numpy_expand(F, key, t):
+    """The expand the reading R10 predicts from the Philox words: up to eight
+    attempts, block (t, a, 2): i = U(w0, r), j = U(w1, r-1) shifted past i,
+    roles = the U(w2, 6)-th permutation of (u, v, w) in lexicographic order,
+    plus when the top bit of w3 is 0, else split (Sec. 3.3.1)."""
+    perms = list(itertools.permutations(range(3)))
+    r = F[0].shape[0]
+    ok = lambda x: np.abs(x).max() <= 1
+    for a in range(8):
+        w0, w1, w2, w3 = O.philox((t & 0xFFFFFFFF, t >> 32, a, 2), key)
+        i = (w0 * r) >> 32
+        j = (w1 * (r - 1)) >> 32
+        j += j >= i
+        X, Y, Z = perms[(w2 * 6) >> 32]
+        G = [f.copy() for f in F]
+        new = [None, None, None]
+        if (w3 >> 31) == 0:
+            # plus: x_i (y_i + y_j) z_i + x_i y_j (z_j - z_i) + (x_j - x_i) y_j z_j
+            if any(np.array_equal(F[k][i], F[k][j]) for k in (X, Y, Z)):
+                continue
+            sy, sz, sx = F[Y][i] + F[Y][j], F[Z][j] - F[Z][i], F[X][j] - F[X][i]
+            if not (ok(sy) and ok(sz) and ok(sx)) or not sy.any():
+                continue
+            new[X], new[Y], new[Z] = sx, F[Y][j].copy(), F[Z][j].copy()
+            G[X][j], G[Z][j], G[Y][i] = F[X][i], sz, sy
+            kind = "plus"
+        else:
+            # split: x_j y_i z_i + (x_i - x_j) y_i z_i
+            if np.array_equal(F[X][i], F[X][j]):
+                continue
+            sx = F[X][i] - F[X][j]
+            if not ok(sx):
+                continue
+            new = [F[0][i].copy(), F[1][i].copy(), F[2][i].copy()]
+            new[X] = sx
+            G[X][i] = F[X][j]
+            kind = "split"
+        G = [np.vstack([G[k], new[k][None, :]]) for k in range(3)]
+        for k in (i, j, r):
+            G[0][k], G[1][k], G[2][k] = _numpy_normalise(G[0][k], G[1][k], G[2][k])
+        return kind, G
+    return None, None
+
+
+def test_expand_sampling_reading():
+    """Strassen's scheme has no flip at all (checked here with the numpy
+    enumeration), so the first iteration of a walk from it is a dead end and
+    Algorithm 1 expands: the oracle's new scheme equals the plus or split the
+    reading predicts, and it stays a valid scheme."""
+    U, V, W = load_formula_scheme("strassen_formulas.txt")[3:]
+    start = O.normalise(O.to_c(U, V, W, 2, 2, 2))
+    d0 = O.from_c(start)
+    F = [d0["U"].astype(np.int64), d0["V"].astype(np.int64), d0["W"].astype(np.int64)]
+    assert not any(_numpy_candidates(F, i, X) for i in range(7) for X in range(3))
+    kinds = set()
+    for seed in range(64):
+        prm = O.make_params(seed=seed, max_iters=10, plateau=10 ** 6, r0=7, r_cap=12)
+        w = O.new_walk(start)
+        O.run(w, prm, 1)
+        kind, G = _numpy_expand(F, (seed & 0xFFFFFFFF, seed >> 32), 1)
+        c = O.counters(w)
+        assert c["dead_ends"] == 1 and c["flips"] == 0
+        if kind is None:
+            assert c["expands"] == 0 and w.cur.r == 7
+            continue
+        kinds.add(kind)
+        d = O.from_c(w.cur)
+        assert c["expands"] == 1 and d["r"] == 8
+        for got, want in zip((d["U"], d["V"], d["W"]), G):
+            assert np.array_equal(got, want), (seed, kind)
+        assert O.brent_violations(w.cur) == 0
+    assert kinds == {"plus", "split"}
