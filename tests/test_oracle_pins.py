@@ -567,3 +567,43 @@ def test_expand_sampling_reading():
             assert np.array_equal(got, want), (seed, kind)
         assert O.brent_violations(w.cur) == 0
     assert kinds == {"plus", "split"}
+
+
+# ------------------------------------------------------- best-scheme gates
+def test_equal_rank_acceptance_reading():
+    """Algorithm 1 keeps the current scheme as the best one when it merely
+    equals the best rank with probability 0.01: reading R11/R12, accepted iff
+    word w0 of block (t, 0, 1) is below round(0.01 * 2^32).  Stepping walks one
+    iteration at a time (iterations without a merge, whose state at the check
+    is the final one), every acceptance and every refusal is predicted."""
+    t_eq = 42949673
+    M32 = 0xFFFFFFFF
+    accepted = refused = 0
+    for seed in range(3):
+        prm = O.make_params(seed=777 + seed, max_iters=10 ** 6, plateau=10 ** 6, r0=27,
+                            t_eq=t_eq)
+        w = O.new_walk(O.standard(3, 3, 3))
+        O.run(w, prm, 300)
+        key = ((777 + seed) & M32, (777 + seed) >> 32)
+        for _ in range(1500):
+            best_rank = w.best_rank
+            best = O.from_c(w.best)
+            c0 = O.counters(w)
+            t = w.t + 1
+            O.run(w, prm, 1)
+            c1 = O.counters(w)
+            if c1["merges"] != c0["merges"] or c1["flips"] == c0["flips"]:
+                continue
+            cur = O.from_c(w.cur)
+            if cur["r"] < best_rank:
+                continue  # a strict improvement
+            g0 = O.philox((t & M32, t >> 32, 0, 1), key)[0]
+            same_best = all(np.array_equal(best[k], O.from_c(w.best)[k]) for k in "UVW")
+            if cur["r"] == best_rank and g0 < t_eq:
+                accepted += 1
+                assert c1["eq_accepts"] == c0["eq_accepts"] + 1
+                assert all(np.array_equal(cur[k], O.from_c(w.best)[k]) for k in "UVW")
+            else:
+                refused += cur["r"] == best_rank
+                assert c1["eq_accepts"] == c0["eq_accepts"] and same_best
+    assert accepted >= 5 and refused >= 100
