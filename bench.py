@@ -49,7 +49,8 @@ def ops_per_iteration(cnt, iters, mean_rank, wd=1):
     """Algorithmic 32-bit integer operations of one walk iteration, from the
     walk's own counters (model stated in the design doc):
       Philox block          100 ops (10 rounds x (4 mul + 4 xor + 2 add)), one per
-                            attempt drawn, per cyclic search, per gate, per expand try
+                            attempt drawn, per gate, per expand try (the cyclic
+                            search uses words of attempt blocks already drawn)
       partner scan          (4*wd + 2) ops per term per attempt, 12*wd per attempt
                             for the validity of the (about one) matching term
       cyclic search         3 pair scans of r terms x (4*wd + 2)
@@ -62,7 +63,7 @@ def ops_per_iteration(cnt, iters, mean_rank, wd=1):
     fb = cnt["fallbacks"] / iters
     exp_blocks = (cnt["expands"] + 8 * cnt["expand_fails"]) / iters
     flips = cnt["flips"] / iters
-    philox = 100.0 * (a + fb + 1.0 + exp_blocks)
+    philox = 100.0 * (a + 1.0 + exp_blocks)
     scan = a * (r * (4 * wd + 2) + 12 * wd)
     cyclic = fb * 3 * r * (4 * wd + 2)
     apply = 30.0 * wd * flips
