@@ -47,7 +47,7 @@ def kernel_sources_sha1():
 
 def ops_per_iteration(cnt, iters, mean_rank, wd=1):
     """Algorithmic 32-bit integer operations of one walk iteration, from the
-    walk's own counters (model stated in the design doc):
+    walk's own counters:
       Philox block          100 ops (10 rounds x (4 mul + 4 xor + 2 add)), one per
                             attempt drawn, per gate, per expand try (the cyclic
                             search uses words of attempt blocks already drawn)
