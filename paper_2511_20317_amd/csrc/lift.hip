@@ -1,8 +1,8 @@
 // lift.hip -- ternary lifting of a Z2 scheme (Sec. 3.10.1) as a parallel
 // exhaustive search on the GPU.
 //
-// The search space and order are those of the oracle's reading: per term the
-// first non-zero entry of u and of v is +1 and the other non-zero entries --
+// The search space and order (a fixed convention, so that the first lifting
+// found is unique): per term the first non-zero entry of u and of v is +1 and the other non-zero entries --
 // u ascending, then v, then w -- are the term's free signs, bit i of the
 // term's pattern x meaning entry i is -1; terms in order, patterns
 // ascending; after a term every equation it touches must stay reachable,

@@ -65,8 +65,9 @@ TSF_HD void normalise_packed(uint64_t (&f)[6])
 }
 
 // Swap sizes: a term of an (m,n,p) scheme -> the term of the (m,p,n) scheme
-// (u'' = w^T, v'' = v^T, w'' = u^T; see the oracle's derivation: C^T = B^T A^T
-// followed by two rotations of the factors), normalised
+// (u'' = w^T, v'' = v^T, w'' = u^T: C^T = B^T A^T, and the Brent equations of
+// the C^T layout are invariant under the cyclic rotation of the three
+// factors), normalised
 TSF_HD void term_swap(const uint64_t (&f)[6], int m, int n, int p, uint64_t (&o)[6])
 {
     o[0] = mask_transpose(f[4], p, m);

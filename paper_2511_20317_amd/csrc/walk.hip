@@ -384,9 +384,9 @@ __global__ void __launch_bounds__(256) best_compact_kernel(const unsigned long l
 
 // Algorithm 2 on every walk (one wavefront per walk): the walk's current or
 // best scheme, after the operators drawn from Philox blocks (round, 0, 3)
-// and (round, 1, 3) of its seed, becomes its start scheme in `out` (the
-// oracle's or_resize states the same reading).  Partners are the best
-// schemes of the table, read from in.best.  Lanes handle output terms.
+// and (round, 1, 3) of its seed, becomes its start scheme in `out`.
+// Partners are the best schemes of the table, read from in.best.  Lanes
+// handle output terms.
 __global__ void __launch_bounds__(64) resize_kernel(tsf_walk_batch in, int32_t which,
                                                     const tsf_best_entry *table,
                                                     const int32_t *n_entries, uint64_t base_seed,
