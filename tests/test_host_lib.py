@@ -296,3 +296,33 @@ def test_meta_swap_merge_product_match_oracle(lib):
     assert tsf.verify(got) == 0
     with pytest.raises(tsf.TsfError):
         tsf.meta_merge(_from_oracle(x), _from_oracle(_walked_oracle((2, 3, 3), 1)), 2)
+
+
+def test_error_paths_of_the_host_calls(lib):
+    """Documented errors of the host calls: null pointers are TSF_E_ARG, a
+    factor longer than 64 entries TSF_E_FORMAT, an output too small
+    TSF_E_CAPACITY, an axis or index out of range TSF_E_ARG; every error leaves
+    a message for tsf_last_error."""
+    assert lib.tsf_init_scheme(2, 2, 2, 0, None) == -1
+    assert lib.tsf_last_error()
+    assert lib.tsf_verify(None, None) == -1
+    n = C.c_int64()
+    assert lib.tsf_verify(None, C.byref(n)) == -1
+    s = tsf.init_scheme(2, 2, 2)
+    assert lib.tsf_verify(C.byref(s.c()), None) == -1
+    # a factor of 8 x 9 = 72 entries does not fit one 64-bit mask
+    with pytest.raises(tsf.TsfError) as e:
+        tsf.init_scheme(8, 9, 1)
+    assert e.value.status == -2
+    # extend of (2,2,2) along p into an output of capacity 9 < 8 + 4
+    out = tsf.Scheme.empty(2, 2, 3, 9)
+    cs = out.c()
+    assert lib.tsf_meta_extend(C.byref(s.c()), 2, C.byref(cs)) == -3
+    # axis and index out of range
+    out = tsf.Scheme.empty(2, 2, 1, 8)
+    cs = out.c()
+    assert lib.tsf_meta_project(C.byref(s.c()), 3, 0, C.byref(cs)) == -1
+    assert lib.tsf_meta_project(C.byref(s.c()), 2, 2, C.byref(cs)) == -1
+    assert b"" != lib.tsf_last_error()
+    # the same calls in range succeed
+    assert lib.tsf_meta_project(C.byref(s.c()), 2, 1, C.byref(cs)) == 0
