@@ -71,7 +71,7 @@ def ops_per_iteration(cnt, iters, mean_rank, wd=1):
     return philox + scan + cyclic + apply + red + 20.0
 
 
-def cpu_baseline(n_walks=256, iters=100000, threads=None):
+def cpu_baseline(n_walks=512, iters=100000, threads=None):
     """The oracle as it stands, on the host cores: (3,3,3) walks from the
     standard scheme with the benchmark's parameters, a bounded sample."""
     from oracle import pyoracle as O
@@ -85,8 +85,9 @@ def cpu_baseline(n_walks=256, iters=100000, threads=None):
     its = sum(w.c.iters for w in ws)
     return {"value": flips / dt, "unit": "flips/s", "cores": threads, "kind": "oracle",
             "sample": "%d walks x %d iterations of the (3,3,3) workload (seeds 0..%d), "
-                      "%.1f s wall, %.3g iterations/s" % (n_walks, iters, n_walks - 1, dt,
-                                                          its / dt)}
+                      "%.1f s wall on %d threads, %.3g iterations/s, %.3g flips/s per core"
+                      % (n_walks, iters, n_walks - 1, dt, threads, its / dt,
+                         flips / dt / threads)}
 
 
 def learned_vs_uniform(ctx, args):
@@ -438,7 +439,7 @@ def main():
                     help="1 attempt-parallel, 2 term-parallel, 3 indexed attempt-parallel "
                          "(0: library choice)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-walks", type=int, default=256)
+    ap.add_argument("--cpu-walks", type=int, default=512)
     ap.add_argument("--cpu-iters", type=int, default=100000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter scale)")
