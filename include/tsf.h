@@ -208,7 +208,8 @@ typedef struct {
     int64_t  plateau;          /* restart after this many iterations without a
                                   strict improvement of the best rank (<= 0: off) */
     int32_t  flip_tries;       /* random flip attempts per iteration (1..64)
-                                  before the exhaustive search                    */
+                                  before the cyclic search over all (term, kind)
+                                  pairs                                           */
     int32_t  restart_from_best;/* restart from the best scheme instead of the start */
     uint64_t t_eq;             /* accept an equal-rank scheme as best (Alg. 1: 0.01) */
     uint64_t t_reduce;         /* p_reduce of Alg. 1                              */
@@ -353,6 +354,15 @@ tsf_status tsf_walk_init(tsf_ctx *ctx, const tsf_walk_batch *b, void *hip_stream
 
 /* Run up to n_iters further iterations of Algorithm 1 on every walk of the
  * batch (a walk stops early at its target rank or its iteration budget).
+ * Random words (the paper leaves the sampling open): iteration t of a walk
+ * uses Philox blocks (t, a, 0) for flip attempt a (term U(w0, r), kind
+ * U(w1, 3), candidate U(w2, n) among the valid partners, role 0 then 1, j
+ * ascending), the fourth words of blocks (t, 0, 0) and (t, 1, 0) for the
+ * start pair and candidate of the cyclic search when every attempt failed,
+ * (t, 0, 1) for the gates (equal-rank acceptance, reduce, expand) and
+ * (t, a, 2) for expand attempt a; U(w, n) = floor(w * n / 2^32).  Results do
+ * not depend on the launch configuration or on how iterations are split
+ * into calls.
  * Asynchronous on `hip_stream`; `launch` may be NULL (library choice).
  * The host validates the batch shape against the chosen kernel; the per-walk
  * headers are device data and are trusted to be what tsf_walk_init and
