@@ -696,12 +696,25 @@ struct Walker {
 #pragma unroll
             for (int c = 0; c < 2 * NW; ++c) {
                 part[c] = 0;
-                for (; k < kend && k < 32 * (c + 1); k += 2) {
+                const int kc = kend < 32 * (c + 1) ? kend : 32 * (c + 1);
+                // four terms per step while four remain, then two
+                for (; k + 2 < kc; k += 4) {
+                    const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2],
+                            s1 = col[2 * k + 3], d2 = col[2 * k + 4], s2 = col[2 * k + 5],
+                            d3 = col[2 * k + 6], s3 = col[2 * k + 7];
+                    const int sh = k - 32 * c;
+                    part[c] |= ((d0 == xi.d) & ((s0 == xi.s) | (s0 == nsi)) ? 1u : 0u) << sh;
+                    part[c] |= ((d1 == xi.d) & ((s1 == xi.s) | (s1 == nsi)) ? 2u : 0u) << sh;
+                    part[c] |= ((d2 == xi.d) & ((s2 == xi.s) | (s2 == nsi)) ? 4u : 0u) << sh;
+                    part[c] |= ((d3 == xi.d) & ((s3 == xi.s) | (s3 == nsi)) ? 8u : 0u) << sh;
+                }
+                if (k < kc) {
                     const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2],
                             s1 = col[2 * k + 3];
                     const uint32_t b0 = 1u << (k - 32 * c), b1 = 2u << (k - 32 * c);
                     part[c] |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
                     part[c] |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
+                    k += 2;
                 }
             }
 #pragma unroll
