@@ -104,6 +104,31 @@ def test_learned_walk_replays_on_oracle(ctx, fmt, r_cap, lanes):
     assert (choices[(choices != 255)] > 0).any()
 
 
+@pytest.mark.parametrize("fmt,r_cap,n_iters", [((3, 3, 3), 35, 200), ((4, 4, 4), 64, 100)])
+def test_learned_walk_full_batch_sampled(ctx, fmt, r_cap, n_iters):
+    """The learned comparison's batch shape (4,096 walks, the default launch):
+    sampled walks replay on the oracle from their logged choices."""
+    s = tsf.init_scheme(*fmt)
+    groups = [(s, 4096, r_cap, 0)]
+    prm = tsf.walk_params(base_seed=3 << 20, max_iters=10 ** 9, plateau=50000)
+    net, _ = _random_net(11)
+    b = tsf.WalkBatch(groups, rec_cap=32)
+    b.init(ctx)
+    ws = tsf.LearnWorkspace(b.n_walks, choice_cap=n_iters)
+    b.walk_learned(ctx, prm, net, ws, n_iters)
+    _sync()
+    choices = ws.choice.cpu().numpy()
+    rng = np.random.default_rng(4)
+    walks = sorted(set(rng.integers(0, 4096, 10).tolist()) | {0, 4095})
+    oracle_walks = {}
+    for w in walks:
+        ow = O.new_walk(oracle_start(s))
+        bad = O.run_choices(ow, oracle_params(prm, w, r_cap, 0), n_iters, choices[w])
+        assert bad == 0, "walk %d: a logged choice is not a valid candidate" % w
+        oracle_walks[w] = ow
+    compare(b, oracle_walks, "learned full %s" % (fmt,))
+
+
 def test_learned_scores_and_choices_at_first_iteration(ctx):
     """Iteration 1 from the start scheme: the proposed candidates and their
     feature rows equal the oracle's, the scores equal the fp64 network within
