@@ -391,6 +391,27 @@ def run_lift(ctx, args):
     return out
 
 
+def run_learned_walk(ctx, args):
+    """Throughput of the learned proposal: 4,096 (3,3,3) walks with a
+    random-initialised network (the cost does not depend on the weights),
+    learned and uniform proposals for args.ab_seconds each."""
+    from paper_2511_20317_amd import learn, tsf
+    s = tsf.init_scheme(3, 3, 3)
+    rng = np.random.default_rng(0)
+    net = tsf.Mlp()
+    net.set_params(rng.standard_normal((512, 256)) * np.sqrt(2 / 64), np.zeros(256),
+                   rng.standard_normal((256, 256)) * np.sqrt(2 / 256), np.zeros(256),
+                   rng.standard_normal(256) * np.sqrt(1 / 256), np.zeros(1))
+    out = {}
+    for mode in ("learned", "uniform"):
+        res = learn.time_to_ranks(ctx, s, args.ab_walks, 35, (26, 25, 24, 23), args.ab_seconds,
+                                  1 << 20, net=net if mode == "learned" else None)
+        out[mode] = {"iterations_per_s": res["iterations"] / res["wall_s"],
+                     "flips_per_s": res["flips"] / res["wall_s"], "wall_s": res["wall_s"],
+                     "best_rank": res["best_rank"]}
+    return out
+
+
 def time_to_rank_fine(ctx, args, target=23, round_iters=1000, limit_s=60.0):
     """Time to the target rank with rounds of round_iters iterations: a fresh
     batch of the (3,3,3) workload is walked round by round (the best rank is
@@ -444,7 +465,8 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter scale)")
     ap.add_argument("--workload", default="333",
-                    choices=["333", "mixed", "large", "additions", "explore", "lift"],
+                    choices=["333", "mixed", "large", "additions", "explore", "lift",
+                             "learned-walk"],
                     help="333: the (3,3,3) benchmark; mixed / large / additions: the other "
                          "workloads")
     ap.add_argument("--learned", action="store_true",
@@ -469,7 +491,8 @@ def main():
     ctx = tsf.Context()
     if args.workload != "333":
         res = {"mixed": run_mixed, "large": run_large, "additions": run_additions,
-               "explore": run_explore, "lift": run_lift}[args.workload](ctx, args)
+               "explore": run_explore, "lift": run_lift,
+               "learned-walk": run_learned_walk}[args.workload](ctx, args)
         if args.workload == "mixed":
             value = res["ternary"]["flips_per_s"]
             desc = ("131,072 walks over (3,3,4), (3,4,5), (4,4,4), (4,4,5) in one launch, "
@@ -481,6 +504,10 @@ def main():
         elif args.workload == "lift":
             value = None
             desc = "ternary lifting of the best Z2 schemes of (2,2,3), (2,3,3), (3,3,3) walks"
+        elif args.workload == "learned-walk":
+            value = res["learned"]["flips_per_s"]
+            desc = ("%d (3,3,3) walks with learned proposals (random-initialised network), "
+                    "then uniform proposals, %.0f s each" % (args.ab_walks, args.ab_seconds))
         elif args.workload == "additions":
             value = res["flips_per_s"]
             desc = ("65,536 (3,3,3) walks minimising naive additions at fixed rank from the best "
@@ -492,9 +519,12 @@ def main():
         out = {"metric": "flips/sec on 1 GPU", "value": value, "unit": "flips/s", "n_gpus": 1,
                "steps": args.steps, "warmup": 0, "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None,
-               "dtype": "u64" if args.workload in ("large", "explore") else "u32",
-               "data": "synthetic", "config": {"workload": desc, "walks": args.walks,
-                                               "iters_per_step": args.iters},
+               "dtype": ("u64" if args.workload in ("large", "explore") else
+                         "u32/bf16" if args.workload == "learned-walk" else "u32"),
+               "data": "synthetic",
+               "config": ({"workload": desc, "walks": args.ab_walks, "seconds": args.ab_seconds}
+                          if args.workload == "learned-walk" else
+                          {"workload": desc, "walks": args.walks, "iters_per_step": args.iters}),
                "results": res}
         print(json.dumps(out))
         return
