@@ -105,6 +105,47 @@ __device__ __forceinline__ void stage(uint16_t (*tile)[LDK], const uint16_t *P, 
     }
 }
 
+// The same staging split in two for operands whose k is contiguous: each
+// thread's two 16-byte pieces of the next tile are read into registers while
+// the current tile is multiplied, then written to LDS.
+static_assert(BM == BN, "one fragment shape for both operands");
+struct Frag {
+    uint4 v[BM * BK / 8 / 256];
+};
+__device__ __forceinline__ void load_frag(Frag &f, const uint16_t *P, int64_t s_row, int rows,
+                                          int K, int r0, int k0)
+{
+#pragma unroll
+    for (int t = 0; t < BM * BK / 8 / 256; ++t) {
+        const int e = threadIdx.x + 256 * t;
+        const int r = e / (BK / 8), kc = (e % (BK / 8)) * 8;
+        const int gr = r0 + r, gk = k0 + kc;
+        const uint16_t *src = P + gr * s_row + gk;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gr < rows) {
+            if (gk + 8 <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+                v = *reinterpret_cast<const uint4 *>(src);
+            } else {
+                uint16_t tmp[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) tmp[q] = (gk + q < K) ? src[q] : (uint16_t)0;
+                v = make_uint4(tmp[0] | (uint32_t)tmp[1] << 16, tmp[2] | (uint32_t)tmp[3] << 16,
+                               tmp[4] | (uint32_t)tmp[5] << 16, tmp[6] | (uint32_t)tmp[7] << 16);
+            }
+        }
+        f.v[t] = v;
+    }
+}
+__device__ __forceinline__ void store_frag(uint16_t (*tile)[LDK], const Frag &f)
+{
+#pragma unroll
+    for (int t = 0; t < BM * BK / 8 / 256; ++t) {
+        const int e = threadIdx.x + 256 * t;
+        const int r = e / (BK / 8), kc = (e % (BK / 8)) * 8;
+        *reinterpret_cast<uint4 *>(&tile[r][kc]) = f.v[t];
+    }
+}
+
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];
@@ -120,10 +161,27 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[a][b][q] = 0.0f;
     const int row = lane & 31, kh = 8 * (lane >> 5);
+    // both operands k-contiguous (the forward pass): the next tile's reads
+    // overlap this tile's products
+    const bool piped = g.a_col == 1 && g.b_col == 1;
+    Frag fa, fb;
+    if (piped) {
+        load_frag(fa, g.A, g.a_row, g.M, g.K, m0, 0);
+        load_frag(fb, g.B, g.b_row, g.N, g.K, n0, 0);
+    }
     for (int k0 = 0; k0 < g.K; k0 += BK) {
-        stage(As, g.A, g.a_row, g.a_col, g.M, g.K, m0, k0);
-        stage(Bs, g.B, g.b_row, g.b_col, g.N, g.K, n0, k0);
+        if (piped) {
+            store_frag(As, fa);
+            store_frag(Bs, fb);
+        } else {
+            stage(As, g.A, g.a_row, g.a_col, g.M, g.K, m0, k0);
+            stage(Bs, g.B, g.b_row, g.b_col, g.N, g.K, n0, k0);
+        }
         __syncthreads();
+        if (piped && k0 + BK < g.K) {
+            load_frag(fa, g.A, g.a_row, g.M, g.K, m0, k0 + BK);
+            load_frag(fb, g.B, g.b_row, g.N, g.K, n0, k0 + BK);
+        }
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             // 32x32x16: lane l holds A[l%32][8*(l/32) + 0..7] and B[l%32][same k]
@@ -143,6 +201,32 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         __syncthreads();
     }
     // accumulator register q of lane l: row 8*(q/4) + 4*(l/32) + q%4, column l%32
+    if (g.ep == EP_BIAS_RELU_BF16 && m0 + BM <= g.M && n0 + BN <= g.N && (g.N & 7) == 0 &&
+        (reinterpret_cast<uintptr_t>(g.out_bf16) & 15) == 0) {
+        // full tile of the forward pass: bias + ReLU + bf16 into LDS, then
+        // 16-byte row-contiguous stores
+        __shared__ __attribute__((aligned(16))) uint16_t Cs[BM][BN + 8];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int cl = wn + 32 * b + (lane & 31);
+                const float bias = g.bias[n0 + cl];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int rl = wm + 32 * a + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    const float v = acc[a][b][q] + bias;
+                    Cs[rl][cl] = to_bf16(v > 0.0f ? v : 0.0f);
+                }
+            }
+        __syncthreads();
+        for (int e = threadIdx.x; e < BM * BN / 8; e += 256) {
+            const int r = e / (BN / 8), c = (e % (BN / 8)) * 8;
+            *reinterpret_cast<uint4 *>(g.out_bf16 + (int64_t)(m0 + r) * g.N + n0 + c) =
+                *reinterpret_cast<const uint4 *>(&Cs[r][c]);
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
