@@ -148,8 +148,12 @@ __device__ __forceinline__ void store_frag(uint16_t (*tile)[LDK], const Frag &f)
 
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDK];
+    // one LDS buffer: the A and B tiles during the products, the output tile
+    // of the forward epilogue afterwards
+    constexpr int kTiles = (BM + BN) * LDK, kOut = BM * (BN + 8);
+    __shared__ __attribute__((aligned(16))) uint16_t smem[kTiles > kOut ? kTiles : kOut];
+    uint16_t (*As)[LDK] = reinterpret_cast<uint16_t (*)[LDK]>(smem);
+    uint16_t (*Bs)[LDK] = reinterpret_cast<uint16_t (*)[LDK]>(smem + BM * LDK);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // this wave's 64x64 sub-tile
@@ -205,7 +209,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         (reinterpret_cast<uintptr_t>(g.out_bf16) & 15) == 0) {
         // full tile of the forward pass: bias + ReLU + bf16 into LDS, then
         // 16-byte row-contiguous stores
-        __shared__ __attribute__((aligned(16))) uint16_t Cs[BM][BN + 8];
+        uint16_t (*Cs)[BN + 8] = reinterpret_cast<uint16_t (*)[BN + 8]>(smem);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
