@@ -7,7 +7,7 @@
 // The three dense products of the forward pass and the three of the backward
 // pass run through one tiled GEMM kernel (128x128 output tile per workgroup,
 // four wavefronts of 64x64 on v_mfma_f32_32x32x16_bf16, K staged through LDS
-// 32 at a time) with fused epilogues: bias + ReLU + bf16 rounding (forward),
+// 64 at a time) with fused epilogues: bias + ReLU + bf16 rounding (forward),
 // ReLU mask + bf16 rounding (backpropagated deltas), plain fp32 (weight
 // gradients).
 #include <hip/hip_runtime.h>
@@ -66,8 +66,8 @@ struct GemmArgs {
 typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 
 // Output tile 128 x 128 per workgroup of four wavefronts (2 x 2 of 64 x 64);
-// K is staged through LDS 32 at a time.
-constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+// K is staged through LDS 64 at a time.
+constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
 
 // Stage a 128 x BK tile of an operand (rows r0.., cols k0..) into LDS as
 // tile[r][k], zero outside the matrix.  When the operand's k is contiguous,
