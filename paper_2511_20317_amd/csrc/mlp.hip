@@ -5,8 +5,8 @@
 //   logit = h2 . w3 + b3;  loss = mean(softplus(logit) - y logit)
 //
 // The three dense products of the forward pass and the three of the backward
-// pass run through one tiled GEMM kernel (128x128 output tile per workgroup,
-// four wavefronts of 64x64 on v_mfma_f32_32x32x16_bf16, K staged through LDS
+// pass run through one tiled GEMM kernel (64x128 output tile per workgroup,
+// four wavefronts of 32x64 on v_mfma_f32_32x32x16_bf16, K staged through LDS
 // 64 at a time) with fused epilogues: bias + ReLU + bf16 rounding (forward),
 // ReLU mask + bf16 rounding (backpropagated deltas), plain fp32 (weight
 // gradients).
@@ -65,20 +65,23 @@ struct GemmArgs {
 
 typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 
-// Output tile 128 x 128 per workgroup of four wavefronts (2 x 2 of 64 x 64);
+// Output tile BM x BN per workgroup of four wavefronts (2 x 2 of WM x 64);
 // K is staged through LDS 64 at a time.
-constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
+constexpr int BM = 64, BN = 128, BK = 64, LDK = BK + 8;
+// wavefront sub-tile: WM x 64, AM blocks of 32 rows
+constexpr int WM = BM / 2, AM = WM / 32;
 
 // Stage a 128 x BK tile of an operand (rows r0.., cols k0..) into LDS as
 // tile[r][k], zero outside the matrix.  When the operand's k is contiguous,
 // each thread moves 8 consecutive elements (16 bytes) at a time; otherwise
 // threads walk the contiguous row dimension so reads still coalesce.
+template <int R>
 __device__ __forceinline__ void stage(uint16_t (*tile)[LDK], const uint16_t *P, int64_t s_row,
                                       int64_t s_col, int rows, int K, int r0, int k0)
 {
     const int tid = threadIdx.x;
     if (s_col == 1) {
-        for (int e = tid; e < BM * BK / 8; e += 256) {
+        for (int e = tid; e < R * BK / 8; e += 256) {
             const int r = e / (BK / 8), kc = (e % (BK / 8)) * 8;
             const int gr = r0 + r, gk = k0 + kc;
             const uint16_t *src = P + gr * s_row + gk;
@@ -97,8 +100,8 @@ __device__ __forceinline__ void stage(uint16_t (*tile)[LDK], const uint16_t *P, 
             *reinterpret_cast<uint4 *>(&tile[r][kc]) = v;
         }
     } else {
-        for (int e = tid; e < BM * BK; e += 256) {
-            const int k = e / BM, r = e % BM;
+        for (int e = tid; e < R * BK; e += 256) {
+            const int k = e / R, r = e % R;
             const int gr = r0 + r, gk = k0 + k;
             tile[r][k] = (gr < rows && gk < K) ? P[gr * s_row + gk * s_col] : (uint16_t)0;
         }
@@ -108,15 +111,17 @@ __device__ __forceinline__ void stage(uint16_t (*tile)[LDK], const uint16_t *P, 
 // The same staging split in two for operands whose k is contiguous: each
 // thread's two 16-byte pieces of the next tile are read into registers while
 // the current tile is multiplied, then written to LDS.
-static_assert(BM == BN, "one fragment shape for both operands");
+template <int R>
 struct Frag {
-    uint4 v[BM * BK / 8 / 256];
+    static_assert(R * BK % (8 * 256) == 0, "whole 16-byte pieces per thread");
+    uint4 v[R * BK / 8 / 256];
 };
-__device__ __forceinline__ void load_frag(Frag &f, const uint16_t *P, int64_t s_row, int rows,
+template <int R>
+__device__ __forceinline__ void load_frag(Frag<R> &f, const uint16_t *P, int64_t s_row, int rows,
                                           int K, int r0, int k0)
 {
 #pragma unroll
-    for (int t = 0; t < BM * BK / 8 / 256; ++t) {
+    for (int t = 0; t < R * BK / 8 / 256; ++t) {
         const int e = threadIdx.x + 256 * t;
         const int r = e / (BK / 8), kc = (e % (BK / 8)) * 8;
         const int gr = r0 + r, gk = k0 + kc;
@@ -136,10 +141,11 @@ __device__ __forceinline__ void load_frag(Frag &f, const uint16_t *P, int64_t s_
         f.v[t] = v;
     }
 }
-__device__ __forceinline__ void store_frag(uint16_t (*tile)[LDK], const Frag &f)
+template <int R>
+__device__ __forceinline__ void store_frag(uint16_t (*tile)[LDK], const Frag<R> &f)
 {
 #pragma unroll
-    for (int t = 0; t < BM * BK / 8 / 256; ++t) {
+    for (int t = 0; t < R * BK / 8 / 256; ++t) {
         const int e = threadIdx.x + 256 * t;
         const int r = e / (BK / 8), kc = (e % (BK / 8)) * 8;
         *reinterpret_cast<uint4 *>(&tile[r][kc]) = f.v[t];
@@ -156,10 +162,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     uint16_t (*Bs)[LDK] = reinterpret_cast<uint16_t (*)[LDK]>(smem + BM * LDK);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // this wave's 64x64 sub-tile
-    v16f32 acc[2][2];
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * 64;  // this wave's WM x 64 sub-tile
+    v16f32 acc[AM][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < AM; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -168,7 +174,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     // both operands k-contiguous (the forward pass): the next tile's reads
     // overlap this tile's products
     const bool piped = g.a_col == 1 && g.b_col == 1;
-    Frag fa, fb;
+    Frag<BM> fa;
+    Frag<BN> fb;
     if (piped) {
         load_frag(fa, g.A, g.a_row, g.M, g.K, m0, 0);
         load_frag(fb, g.B, g.b_row, g.N, g.K, n0, 0);
@@ -178,8 +185,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
             store_frag(As, fa);
             store_frag(Bs, fb);
         } else {
-            stage(As, g.A, g.a_row, g.a_col, g.M, g.K, m0, k0);
-            stage(Bs, g.B, g.b_row, g.b_col, g.N, g.K, n0, k0);
+            stage<BM>(As, g.A, g.a_row, g.a_col, g.M, g.K, m0, k0);
+            stage<BN>(Bs, g.B, g.b_row, g.b_col, g.N, g.K, n0, k0);
         }
         __syncthreads();
         if (piped && k0 + BK < g.K) {
@@ -189,15 +196,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             // 32x32x16: lane l holds A[l%32][8*(l/32) + 0..7] and B[l%32][same k]
-            v8bf16 av[2], bv[2];
+            v8bf16 av[AM], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < AM; ++a)
                 av[a] = *reinterpret_cast<const v8bf16 *>(&As[wm + 32 * a + row][kk + kh]);
 #pragma unroll
             for (int b = 0; b < 2; ++b)
                 bv[b] = *reinterpret_cast<const v8bf16 *>(&Bs[wn + 32 * b + row][kk + kh]);
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < AM; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
@@ -211,7 +218,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         // 16-byte row-contiguous stores
         uint16_t (*Cs)[BN + 8] = reinterpret_cast<uint16_t (*)[BN + 8]>(smem);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < AM; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int cl = wn + 32 * b + (lane & 31);
@@ -232,7 +239,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         return;
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < AM; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int col = n0 + wn + 32 * b + (lane & 31);
