@@ -316,9 +316,9 @@ typedef struct {
  * wavefront; 4 to 32 for the attempt-parallel strategies, 8 to 64 for the
  * term-parallel one).  waves_per_block: 1..4.  A zero field lets the library
  * choose (a launch chosen by tsf_autotune for batches of this shape, else
- * strategy 3 with 8 lanes and 1 wavefront per workgroup up to capacity 64,
- * strategy 1 with the same shape up to capacity 128 when max_len <= 32,
- * strategy 2 with 64 lanes and 4 wavefronts otherwise).
+ * strategy 3 with 8 lanes up to capacity 64, strategy 1 with 8 lanes up to
+ * capacity 128 when max_len <= 32, strategy 2 with 64 lanes otherwise; one
+ * wavefront per workgroup).
  * Results never depend on it. */
 typedef struct {
     int32_t lanes_per_walk;

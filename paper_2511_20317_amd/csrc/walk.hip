@@ -755,11 +755,12 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     int strategy = launch ? launch->strategy : 0;
     if (strategy < 0 || strategy > 3) return tsf_fail(TSF_E_ARG, "strategy %d not in 0..3", strategy);
     // default: the indexed strategy up to 64 terms; the plain attempt-parallel
-    // one up to 128 terms of 32-bit factors (with 64-bit factors its 8 walks
-    // per wavefront would hold 48 KiB of LDS per wavefront at 128 terms);
-    // the term-parallel one beyond
-    if (strategy == 0)
-        strategy = b->capacity <= 64 ? 3 : (b->capacity <= 128 && b->max_len <= 32 ? 1 : 2);
+    // one up to 128 terms of 32-bit factors; the term-parallel one beyond and
+    // for 64-bit factors (measured on the exploratory workload, capacity 128:
+    // its LDS per walk keeps the attempt-parallel kernels at few wavefronts
+    // per CU once the schemes grow)
+    const bool wide = b->max_len > 32;
+    if (strategy == 0) strategy = b->capacity <= 64 ? 3 : (b->capacity <= 128 && !wide ? 1 : 2);
     const bool ap = strategy == 1 || strategy == 3;
     const bool ix = strategy == 3;
     if (ix && b->capacity > 64)
@@ -767,7 +768,7 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (ap && b->capacity > 128)
         return tsf_fail(TSF_E_CAPACITY, "the attempt-parallel strategy needs capacity <= 128");
     int g = launch && launch->lanes_per_walk ? launch->lanes_per_walk : (ap ? 8 : 64);
-    int wpb = launch && launch->waves_per_block ? launch->waves_per_block : (ap ? 1 : 4);
+    int wpb = launch && launch->waves_per_block ? launch->waves_per_block : 1;
     if (g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
         return tsf_fail(TSF_E_ARG, "lanes_per_walk %d not in {4,8,16,32,64}", g);
     if (g == 4 && !ap)
@@ -781,7 +782,6 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (s < 0)
         return tsf_fail(TSF_E_CAPACITY, "capacity %d needs more than 8 slots at %d lanes/walk",
                         b->capacity, g);
-    const bool wide = b->max_len > 32;
     L.fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, strategy);
     if (!L.fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
     const size_t word = wide ? 8 : 4;

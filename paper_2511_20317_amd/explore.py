@@ -27,9 +27,11 @@ def _archive_update(archive, batch, table, count, hdr):
 
 
 def explore(ctx, groups, rounds, iters, capacity, base_seed=0, t_resize=tsf.ALWAYS, plateau=20000,
-            r_cap_extra=8, slots=4096, walk_kw=None):
-    """groups: start schemes as for WalkBatch (one mode).  Returns the archive
-    {format: (best rank, Scheme)} and per-round statistics."""
+            r_cap_extra=8, slots=4096, walk_kw=None, launch=(0, 0, 0)):
+    """groups: start schemes as for WalkBatch (one mode).  launch: (lanes per
+    walk, wavefronts per workgroup, strategy) of the walk calls, zeros for the
+    library's choice.  Returns the archive {format: (best rank, Scheme)} and
+    per-round statistics."""
     a = tsf.WalkBatch(groups, capacity=capacity, rec_cap=4)
     a.max_len = 64
     b = tsf.WalkBatch.empty(a.n_walks, capacity, a.mode, max_len=64, rec_cap=4)
@@ -39,7 +41,7 @@ def explore(ctx, groups, rounds, iters, capacity, base_seed=0, t_resize=tsf.ALWA
     for q in range(rounds):
         prm = tsf.walk_params(base_seed=base_seed + q * a.n_walks, max_iters=iters,
                               plateau=plateau, **kw)
-        a.walk(ctx, prm, iters)
+        a.walk(ctx, prm, iters, *launch)
         table, count = a.population_best(slots)
         hdr = a.headers()
         ent = _archive_update(archive, a, table, count, hdr)
