@@ -4,9 +4,10 @@ time to reach rank 23 at (3,3,3).
 Workload (defaults): format (3,3,3), ternary, 65,536 walks from the standard
 rank-27 scheme, walk seeds 0..65535, at most 1e6 iterations per walk, plateau
 restart after 5e4 iterations without improvement, target rank 23, uniform
-flip proposals.  One step = one round of `--iters` iterations of every walk
-(the walk kernel) followed by the GPU Brent check of every walk's best scheme;
-the default 10 timed steps of 1e5 iterations cover the whole 1e6 budget.
+flip proposals.  One step = one walk-kernel launch of every walk followed by
+the GPU Brent check of every walk's best scheme; the 1e6-iteration budget is
+split evenly over the timed steps (--steps 20: 5e4 iterations per launch), so
+every timed launch does work.
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
 build measures one GPU.
@@ -25,14 +26,17 @@ sys.path.insert(0, ROOT)
 PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x int32 lanes/clk/CU x clock = 39.3e12 op/s
 PEAK_HBM = 8.0e12
 
-# HBM bytes per walk-kernel launch of the default workload (65,536 walks, 10
-# launches of 1e5 iterations), from two rocprofv3 passes over this script:
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per dispatch, the scales read off a
-# 1 GiB device copy in the same runs (--calibrate-copy-mib 1024), averaged
-# over the ten launches.  Valid only for the kernel sources it was measured
-# on (their SHA-1 below); otherwise the benchmark reports no traffic.
-MEASURED_TRAFFIC = {"sources_sha1": "646017e7969f330516ad4d1ad04ad0b72abf9f17", "walks": 65536,
-                    "iters": 100000, "steps": 10, "bytes_per_launch": 1714503797}
+MAX_ITERS = 1000000
+
+# HBM bytes per walk-kernel launch of the default workload (65,536 walks,
+# launches of `iters` iterations each), from two rocprofv3 passes over this
+# script: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per dispatch, the scales read
+# off a 1 GiB device copy in the same runs (--calibrate-copy-mib 1024),
+# averaged over the timed launches.  Valid only for the kernel sources it was
+# measured on (their SHA-1 below) and for launches of the same size;
+# otherwise the benchmark reports no traffic.
+MEASURED_TRAFFIC = {"sources_sha1": None, "walks": 65536, "iters": 50000,
+                    "bytes_per_launch": None}
 KERNEL_SOURCES = ("walk_kernel.h", "walk_inst.hip", "tsf_bits.h")
 
 
@@ -45,30 +49,22 @@ def kernel_sources_sha1():
     return h.hexdigest()
 
 
-def ops_per_iteration(cnt, iters, mean_rank, wd=1):
-    """Algorithmic 32-bit integer operations of one walk iteration, from the
-    walk's own counters:
-      Philox block          100 ops (10 rounds x (4 mul + 4 xor + 2 add)), one per
-                            attempt drawn, per gate, per expand try (the cyclic
-                            search uses words of attempt blocks already drawn)
-      partner scan          (4*wd + 2) ops per term per attempt, 12*wd per attempt
-                            for the validity of the (about one) matching term
-      cyclic search         3 pair scans of r terms x (4*wd + 2)
-      flip + normalisation  30*wd
-      reduction scan        2 modified terms x r x (7*wd + 2)
-      bookkeeping           20
+def ops_per_flip(mean_rank, attempts_per_iteration, fallback_rate, wd=1):
+    """Algorithmic 32-bit integer operations per applied flip, the work model
+    A(r, Wd) of the hot path (Wd = 32-bit words per factor mask, r the mean
+    rank, T the measured attempts per iteration):
+      Philox blocks          100 (T + 1)      (10 rounds x (4 mul + 4 xor + 2 add),
+                                               one per attempt and the gate block)
+      partner tests          T r (4 Wd + 4)   (equality and negated equality of
+                                               the X factor, validity of two roles)
+      apply, normalise and   30 r Wd
+      the reduction scan
+      bookkeeping            80
+      cyclic fallback        3 r (4 Wd + 4)   per iteration that needs it
     """
-    r = mean_rank
-    a = cnt["attempts"] / iters
-    fb = cnt["fallbacks"] / iters
-    exp_blocks = (cnt["expands"] + 8 * cnt["expand_fails"]) / iters
-    flips = cnt["flips"] / iters
-    philox = 100.0 * (a + 1.0 + exp_blocks)
-    scan = a * (r * (4 * wd + 2) + 12 * wd)
-    cyclic = fb * 3 * r * (4 * wd + 2)
-    apply = 30.0 * wd * flips
-    red = 2 * r * (7 * wd + 2) * flips
-    return philox + scan + cyclic + apply + red + 20.0
+    r, t = mean_rank, attempts_per_iteration
+    return (100.0 * (t + 1.0) + t * r * (4 * wd + 4) + 30.0 * r * wd + 80.0 +
+            fallback_rate * 3.0 * r * (4 * wd + 4))
 
 
 def cpu_baseline(n_walks=512, iters=100000, threads=None):
@@ -450,9 +446,11 @@ def time_to_rank_fine(ctx, args, target=23, round_iters=1000, limit_s=60.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--iters", type=int, default=100000, help="iterations per walk per step")
+    ap.add_argument("--iters", type=int, default=0,
+                    help="iterations per walk per step (0: the (3,3,3) workload splits its 1e6 "
+                         "budget evenly over the steps; the other workloads take 1e5)")
     ap.add_argument("--walks", type=int, default=65536)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per walk (0: library choice)")
     ap.add_argument("--wpb", type=int, default=0, help="waves per workgroup (0: library choice)")
@@ -490,6 +488,7 @@ def main():
     torch.cuda.set_device(0)
     ctx = tsf.Context()
     if args.workload != "333":
+        args.iters = args.iters or 100000
         res = {"mixed": run_mixed, "large": run_large, "additions": run_additions,
                "explore": run_explore, "lift": run_lift,
                "learned-walk": run_learned_walk}[args.workload](ctx, args)
@@ -529,39 +528,51 @@ def main():
         print(json.dumps(out))
         return
     target = 23
+    iters_per_step = args.iters or -(-MAX_ITERS // args.steps)
     groups = [(tsf.init_scheme(3, 3, 3), args.walks, 35, target)]
-    prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
+    prm = tsf.walk_params(base_seed=0, max_iters=MAX_ITERS, plateau=50000)
     batch = tsf.WalkBatch(groups, rec_cap=32)
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
         batch.init(ctx)
-        batch.walk(ctx, prm, args.iters, args.lanes, args.wpb, args.strategy)
+        batch.walk(ctx, prm, iters_per_step, args.lanes, args.wpb, args.strategy)
         batch.verify_device(1)
     torch.cuda.synchronize()
 
     batch.init(ctx)
     hdr0 = torch.cuda.synchronize() or batch.headers()
-    best_col = batch.hdr.view(torch.int32).view(args.walks, 40)[:, 7]
+    i32 = batch.hdr.view(torch.int32).view(args.walks, 40)
+    i64 = batch.hdr.view(torch.int64).view(args.walks, 20)
+    best_col, rank_col, iters_col, flips_col = i32[:, 7], i32[:, 6], i64[:, 8], i64[:, 9]
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     ladder = {}
     bad_total = 0
+    step_iters, step_flips, mean_ranks = [], [], [float(hdr0["rank"].mean())]
+    last_iters, last_flips = 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(stream)
-        batch.walk(ctx, prm, args.iters, args.lanes, args.wpb, args.strategy)
+        batch.walk(ctx, prm, iters_per_step, args.lanes, args.wpb, args.strategy)
         ev[k][1].record(stream)
         nv = batch.verify_device(1)
         bad_total += int((nv != 0).sum().item())
-        best_now = int(best_col.min().item())  # synchronises: round granularity
+        # one read-back per step (the loop is synchronous at step granularity)
+        state = torch.stack([best_col.min().to(torch.int64), iters_col.sum(), flips_col.sum(),
+                             rank_col.to(torch.int64).sum()]).tolist()
+        best_now = int(state[0])
+        step_iters.append(state[1] - last_iters)
+        step_flips.append(state[2] - last_flips)
+        last_iters, last_flips = state[1], state[2]
+        mean_ranks.append(state[3] / args.walks)
         now = time.perf_counter() - t0
         for rank in (26, 25, 24, 23):
             if best_now <= rank and rank not in ladder:
                 ladder[rank] = now
-        print("step %d/%d: %.2f s, best rank %d" % (k + 1, args.steps, now, best_now),
-              file=sys.stderr, flush=True)
+        print("step %d/%d: %.2f s, %d iterations, best rank %d" %
+              (k + 1, args.steps, now, step_iters[-1], best_now), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if args.calibrate_copy_mib:
@@ -581,15 +592,20 @@ def main():
     flips = cnt["flips"]
     iters = max(cnt["iters"], 1)
     value = flips / wall
-    mean_rank = float(hdr["rank"].mean())
-    per_launch_iters = iters / args.steps
-    ops_iter = ops_per_iteration(cnt, iters, (mean_rank + 27) / 2)
-    avg_ms = float(np.mean(kernel_ms))
-    achieved = ops_iter * per_launch_iters / (avg_ms * 1e-3)
+    # launches that did work (all of them unless every walk stopped early)
+    working = [k for k in range(args.steps) if step_iters[k] > 0]
+    avg_ms = float(np.mean([kernel_ms[k] for k in working])) if working else None
+    work_flips = sum(step_flips[k] for k in working)
+    # the mean rank over the run: the average of the per-step means
+    # (trapezoid over the step boundaries)
+    mean_rank = float(np.mean([(a + b) / 2 for a, b in zip(mean_ranks[:-1], mean_ranks[1:])]))
+    t_eff = cnt["attempts"] / iters
+    a_op = ops_per_flip(mean_rank, t_eff, cnt["fallbacks"] / iters)
+    achieved = (a_op * work_flips / len(working)) / (avg_ms * 1e-3) if working else 0.0
     traffic = None
     mt = MEASURED_TRAFFIC
     if (mt["bytes_per_launch"] and mt["sources_sha1"] == kernel_sources_sha1() and
-            (args.walks, args.iters, args.steps) == (mt["walks"], mt["iters"], mt["steps"])):
+            (args.walks, iters_per_step) == (mt["walks"], mt["iters"])):
         traffic = mt["bytes_per_launch"]
     # first iteration at which some walk recorded the target rank (records
     # are (iteration, rank) of every strict improvement), and its wall time at
@@ -604,6 +620,7 @@ def main():
         if hit.size and (first_hit is None or hit.min() < first_hit):
             first_hit = int(hit.min())
     ranks = np.bincount(hdr["best_rank"], minlength=28)
+    fine = time_to_rank_fine(ctx, args, target)
     out = {
         "metric": "flips/sec on 1 GPU and time-to-rank-23 at (3,3,3), learned vs uniform proposal",
         "value": value,
@@ -619,24 +636,23 @@ def main():
         "data": "synthetic",
         "config": {"workload": "(3,3,3) ternary walks from the standard rank-27 scheme, "
                                "uniform proposals", "walks": args.walks,
-                   "iters_per_step": args.iters, "max_iters": 1000000, "plateau": 50000,
+                   "iters_per_step": iters_per_step, "max_iters": MAX_ITERS, "plateau": 50000,
                    "target_rank": target, "seeds": "0..%d" % (args.walks - 1),
                    "lanes_per_walk": args.lanes or "library", "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / PEAK_INT32_OPS, "traffic": traffic,
                      "kernel": "walk_kernel", "kernel_avg_ms": avg_ms,
-                     "ops_per_iteration": ops_iter},
-        "time_to_rank_s": ladder,
-        "time_to_rank_23_s": ladder.get(23),
+                     "working_launches": len(working), "ops_per_flip": a_op,
+                     "mean_rank": mean_rank, "attempts_per_iteration": t_eff},
+        "time_to_rank_23_s": fine["time_to_rank_23_s"],
+        "time_to_rank_23_fine": fine,
+        "time_to_rank_s_at_step_ends": ladder,
         "first_rank_23_iteration": first_hit,
-        "time_to_rank_23_at_iteration_rate_s": (first_hit * wall / (iters / args.walks)
-                                                if first_hit is not None else None),
         "walks_at_rank": {str(r): int(ranks[r]) for r in range(20, 28) if ranks[r]},
         "iterations_per_s": iters / wall,
-        "attempts_per_iteration": cnt["attempts"] / iters,
+        "attempts_per_iteration": t_eff,
         "fallback_rate": cnt["fallbacks"] / iters,
         "best_schemes_failing_brent": bad_total,
-        "time_to_rank_23_fine": time_to_rank_fine(ctx, args, target),
         "learned_vs_uniform": None,
     }
     if args.learned:

@@ -375,7 +375,10 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
  * scheme per walk of the batch: which = 0 checks cur (rank hdr[w].rank),
  * 1 checks best (hdr[w].best_rank), 2 checks start (hdr[w].start_rank).
  * n_violated (device, n_walks int64) receives the number of failed
- * equations per walk (0 = valid).  Asynchronous on `hip_stream`.
+ * equations per walk plus the number of mask bits that encode no
+ * coefficient (a digit at or beyond the factor's length, a sign bit without
+ * its digit, any sign bit of a Z2 scheme), so 0 = valid; -1 for a walk whose
+ * header does not fit the batch.  Asynchronous on `hip_stream`.
  * Errors: TSF_E_ARG, TSF_E_DEVICE. */
 tsf_status tsf_verify_batch(const tsf_walk_batch *b, int32_t which, int64_t *n_violated,
                             void *hip_stream);

@@ -72,7 +72,10 @@ __global__ void __launch_bounds__(64) init_kernel(tsf_walk_header *hdr, uint64_t
 // Brent verification (Eq. 1, C^T form of Sec. 3.1) of one scheme per
 // workgroup: the tensor sum_l u_l (x) v_l (x) w_l is built one u-entry slice
 // at a time in LDS (int32 atomics over the non-zero products), then compared
-// with the matrix multiplication tensor.
+// with the matrix multiplication tensor.  A mask bit that encodes no
+// coefficient (a digit at or beyond the factor's length, a sign without its
+// digit, any sign of a Z2 scheme) counts as one violation of its own and
+// takes no part in the tensor.
 __global__ void __launch_bounds__(256) verify_kernel(const tsf_walk_header *hdr,
                                                      const uint64_t *schemes, int32_t cap,
                                                      int32_t n_walks, int32_t which,
@@ -94,6 +97,14 @@ __global__ void __launch_bounds__(256) verify_kernel(const tsf_walk_header *hdr,
     const uint64_t *sc = schemes + (size_t)q * cap * 6;
     if (threadIdx.x == 0) bad_sh = 0;
     int32_t bad = 0;
+    const uint64_t lim[3] = {Lu == 64 ? ~0ull : (1ull << Lu) - 1, Lv == 64 ? ~0ull : (1ull << Lv) - 1,
+                             Lw == 64 ? ~0ull : (1ull << Lw) - 1};
+    for (int l = threadIdx.x; l < rank; l += blockDim.x)
+        for (int X = 0; X < 3; ++X) {
+            const uint64_t d = sc[l * 6 + 2 * X], sg = sc[l * 6 + 2 * X + 1];
+            bad += __builtin_popcountll(d & ~lim[X]) +
+                   __builtin_popcountll(z2 ? sg : (sg & ~(d & lim[X])));
+        }
     for (int av = 0; av < Lu; ++av) {
         for (int e = threadIdx.x; e < Lv * Lw; e += blockDim.x) slice[e] = 0;
         __syncthreads();
@@ -102,10 +113,10 @@ __global__ void __launch_bounds__(256) verify_kernel(const tsf_walk_header *hdr,
             const uint64_t ud = sc[l * 6 + 0], us = sc[l * 6 + 1];
             if (!((ud >> av) & 1)) continue;
             const int su = ((us >> av) & 1) ? -1 : 1;
-            for (uint64_t dv = sc[l * 6 + 2]; dv; dv &= dv - 1) {
+            for (uint64_t dv = sc[l * 6 + 2] & lim[1]; dv; dv &= dv - 1) {
                 const int b = __builtin_ctzll(dv);
                 const int sv = ((sc[l * 6 + 3] >> b) & 1) ? -su : su;
-                for (uint64_t dw = sc[l * 6 + 4]; dw; dw &= dw - 1) {
+                for (uint64_t dw = sc[l * 6 + 4] & lim[2]; dw; dw &= dw - 1) {
                     const int c = __builtin_ctzll(dw);
                     atomicAdd(&slice[b * Lw + c], ((sc[l * 6 + 5] >> c) & 1) ? -sv : sv);
                 }
@@ -674,6 +685,7 @@ bool launch_is_default(const tsf_launch *l)
 {
     return !l || (l->lanes_per_walk == 0 && l->waves_per_block == 0 && l->strategy == 0);
 }
+
 }  // namespace
 
 extern "C" {

@@ -208,10 +208,10 @@ def test_config5_full_batch_sampled(ctx):
     fmts = [(4, 5, 12), (5, 6, 10), (6, 7, 9)]
     groups = [(_std(*f), 32768, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
     prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
-    b = _run(ctx, groups, prm, 150, lanes=64, wpb=1)
+    b = _run(ctx, groups, prm, 2000, lanes=64, wpb=1)
     rng = np.random.default_rng(5)
     walks = sorted({int(q * 32768 + x) for q in range(3) for x in rng.integers(0, 32768, 3)})
-    ow = run_oracle(groups, prm, walks, 150, threads=9)
+    ow = run_oracle(groups, prm, walks, 2000, threads=9)
     compare(b, ow, "cfg5")
     assert (b.verify_device(which=1).cpu().numpy() == 0).all()
     n = b.n_walks
