@@ -414,10 +414,22 @@ tsf_status tsf_population_best(const tsf_walk_batch *b, tsf_best_entry *table, i
  * best scheme of the table (axes p, m, n: the first that exists and fits);
  * if there was none, with probability t_resize/2^32 one of project (5%),
  * product with a best scheme (50%), double (30%), extend (15%).  Random words:
- * Philox4x32-10 blocks (round, 0, 3) and (round, 1, 3) keyed by base_seed +
- * first_walk_id + w; the exact use of each word is the oracle's or_resize.
+ * Philox4x32-10 blocks b0 = (round, 0, 3) and b1 = (round, 1, 3) keyed by
+ * base_seed + first_walk_id + w, U(x, n) = (x * n) >> 32:
+ *   b0.w0 < 2^31           swap sizes, (m,n,p) -> (m,p,n) (before the rest);
+ *   b0.w1                  merge partner table[U(b0.w1, n_entries)], axes
+ *                          tried in the order p, m, n (the first that matches
+ *                          and fits);
+ *   b0.w2 < t_resize       (only without a merge) resize with one operator,
+ *                          chosen by b0.w3 against round(0.05 * 2^32),
+ *                          round(0.55 * 2^32), round(0.85 * 2^32): project /
+ *                          product / double / extend;
+ *   b1.w0                  product partner table[U(b1.w0, n_entries)];
+ *   b1.w1                  axis U(b1.w1, 3) (0 = m, 1 = n, 2 = p) of project,
+ *                          double and extend;
+ *   b1.w2                  project index U(b1.w2, size of that axis).
  * An operator whose result would not fit (a factor over 64 entries, rank over
- * out->capacity) is skipped.  out->hdr[w] receives the format, mode, target,
+ * out->capacity), or a project of an axis of size 1, is skipped.  out->hdr[w] receives the format, mode, target,
  * start_rank and r_cap = min(start_rank + r_cap_extra, out->capacity);
  * follow with tsf_walk_init(out).  applied (optional, device, n_walks int32):
  * the operators applied, bit 0 swap, 1 merge, 2 project, 3 product, 4 double,
