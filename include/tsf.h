@@ -408,6 +408,22 @@ typedef struct {
 tsf_status tsf_population_best(const tsf_walk_batch *b, tsf_best_entry *table, int32_t *n_entries,
                                uint64_t *work, int32_t slots, void *hip_stream);
 
+/* tsf_population_best for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same table from the same kernels, with no workspace argument.  The
+ * working memory is a fixed array inside the library, 2*4096 + 1 uint64
+ * (64 KiB) on each device it runs on, held until the process ends; slots is
+ * limited to its size (1..4096, else TSF_E_ARG).  No call allocates or frees
+ * memory.  Every call on a device uses that device's one array, and the
+ * array keeps the last call's contents (each call clears what it reads):
+ * calls that overlap on one device (two streams, two threads) race and must
+ * be ordered by the caller.  dropped (optional, device int32) receives the
+ * number of walks whose format did not fit `slots`.  Async on the stream.
+ * Errors: TSF_E_ARG, TSF_E_DEVICE. */
+tsf_status tsf_population_best_noalloc(const tsf_walk_batch *b, tsf_best_entry *table,
+                                       int32_t *n_entries, int32_t slots, int32_t *dropped,
+                                       void *hip_stream);
+
 /* Resize (Algorithm 2, Sec. 3.4.3) of every walk, on the GPU: the current
  * (which = 0) or best (1) scheme of walk w of `in` becomes the start scheme
  * of walk w of `out` after: with probability 1/2 swap sizes; a merge with a

@@ -6,6 +6,7 @@
 #include "tsf_meta.h"
 
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace tsfk {
@@ -360,7 +361,9 @@ constexpr int kMaxSlots = 4096;
 __global__ void __launch_bounds__(256) best_compact_kernel(const unsigned long long *keys,
                                                            const unsigned long long *vals,
                                                            int slots, tsf_best_entry *table,
-                                                           int32_t *n_entries)
+                                                           int32_t *n_entries,
+                                                           const int32_t *overflow,
+                                                           int32_t *dropped)
 {
     __shared__ uint32_t ord[kMaxSlots];
     __shared__ int32_t used;
@@ -390,7 +393,10 @@ __global__ void __launch_bounds__(256) best_compact_kernel(const unsigned long l
         e.walk = (int64_t)(vals[q] & 0xFFFFFFFFull);
         table[pos] = e;
     }
-    if (threadIdx.x == 0) *n_entries = used;
+    if (threadIdx.x == 0) {
+        *n_entries = used;
+        if (dropped) *dropped = *overflow;
+    }
 }
 
 // Algorithm 2 on every walk (one wavefront per walk): the walk's current or
@@ -686,6 +692,58 @@ bool launch_is_default(const tsf_launch *l)
     return !l || (l->lanes_per_walk == 0 && l->waves_per_block == 0 && l->strategy == 0);
 }
 
+// The three launches of the population synchronisation over a table of
+// `slots` keys and values and an overflow counter in `work` (2*slots + 1
+// words); the clear kernel writes every word the others read, so the table
+// may hold anything before.
+tsf_status launch_population(const tsf_walk_batch *b, tsf_best_entry *table, int32_t *n_entries,
+                             uint64_t *work, int32_t slots, int32_t *dropped, hipStream_t s)
+{
+    unsigned long long *keys = (unsigned long long *)work, *vals = keys + slots;
+    int32_t *overflow = (int32_t *)(vals + slots);
+    hipLaunchKernelGGL(clear_table_kernel, dim3((slots + 255) / 256), dim3(256), 0, s, keys, vals,
+                       slots, overflow);
+    if (b->n_walks > 0)
+        hipLaunchKernelGGL(best_insert_kernel, dim3((b->n_walks + 255) / 256), dim3(256), 0, s,
+                           b->hdr, b->n_walks, keys, vals, slots, overflow);
+    hipLaunchKernelGGL(best_compact_kernel, dim3(1), dim3(256), 0, s, keys, vals, slots, table,
+                       n_entries, (const int32_t *)overflow, dropped);
+    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "population launch failed");
+    return TSF_OK;
+}
+
+// Working memory of tsf_population_best_noalloc: the table at its largest
+// size (kMaxSlots keys, kMaxSlots values, the overflow counter), one copy on
+// every device the library runs on, for the life of the process.  Host code
+// never passes the array's name to a kernel (on the host it only stands for
+// the symbol): it uses the device address hipGetSymbolAddress returns, looked
+// up once per device.
+__device__ __align__(256) uint64_t scratch[2 * kMaxSlots + 1];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+uint64_t *scratch_ptr[kMaxDevices];
+
+// the current device's copy of `scratch`
+tsf_status population_scratch(uint64_t **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return tsf_fail(TSF_E_DEVICE, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices)
+        return tsf_fail(TSF_E_DEVICE, "device %d beyond the %d the library supports", dev,
+                        kMaxDevices);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return tsf_fail(TSF_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s",
+                            hipGetErrorString(e));
+        scratch_ptr[dev] = (uint64_t *)p;
+    }
+    *out = scratch_ptr[dev];
+    return TSF_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1105,18 +1163,22 @@ tsf_status tsf_population_best(const tsf_walk_batch *b, tsf_best_entry *table, i
     if (slots < 1 || slots > kMaxSlots)
         return tsf_fail(TSF_E_ARG, "slots %d outside [1, %d]", slots, kMaxSlots);
     if (!table || !n_entries || !work) return tsf_fail(TSF_E_ARG, "null table or workspace");
-    hipStream_t s = (hipStream_t)hip_stream;
-    unsigned long long *keys = (unsigned long long *)work, *vals = keys + slots;
-    int32_t *overflow = (int32_t *)(vals + slots);
-    hipLaunchKernelGGL(clear_table_kernel, dim3((slots + 255) / 256), dim3(256), 0, s, keys, vals,
-                       slots, overflow);
-    if (b->n_walks > 0)
-        hipLaunchKernelGGL(best_insert_kernel, dim3((b->n_walks + 255) / 256), dim3(256), 0, s,
-                           b->hdr, b->n_walks, keys, vals, slots, overflow);
-    hipLaunchKernelGGL(best_compact_kernel, dim3(1), dim3(256), 0, s, keys, vals, slots, table,
-                       n_entries);
-    if (hipGetLastError() != hipSuccess) return tsf_fail(TSF_E_DEVICE, "population launch failed");
-    return TSF_OK;
+    return launch_population(b, table, n_entries, work, slots, nullptr, (hipStream_t)hip_stream);
+}
+
+tsf_status tsf_population_best_noalloc(const tsf_walk_batch *b, tsf_best_entry *table,
+                                       int32_t *n_entries, int32_t slots, int32_t *dropped,
+                                       void *hip_stream)
+{
+    tsf_status st = check_batch(b);
+    if (st) return st;
+    if (slots < 1 || slots > kMaxSlots)
+        return tsf_fail(TSF_E_ARG, "slots %d outside [1, %d] (the size of the library's table)",
+                        slots, kMaxSlots);
+    if (!table || !n_entries) return tsf_fail(TSF_E_ARG, "null table or count");
+    uint64_t *work = nullptr;
+    if ((st = population_scratch(&work))) return st;
+    return launch_population(b, table, n_entries, work, slots, dropped, (hipStream_t)hip_stream);
 }
 
 tsf_status tsf_resize_batch(const tsf_walk_batch *in, int32_t which, const tsf_best_entry *table,

@@ -161,6 +161,8 @@ def lib():
             ("tsf_meta_product", [P(CScheme), P(CScheme), P(CScheme)]),
             ("tsf_population_best", [P(WalkBatchC), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_int32, C.c_void_p]),
+            ("tsf_population_best_noalloc", [P(WalkBatchC), C.c_void_p, C.c_void_p,
+                                             C.c_int32, C.c_void_p, C.c_void_p]),
             ("tsf_resize_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p,
                                   P(ResizeParams), P(WalkBatchC), C.c_void_p, C.c_void_p]),
             ("tsf_invariants_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p,
@@ -521,6 +523,16 @@ class WalkBatch:
         check(lib().tsf_population_best(C.byref(self.c()), C.c_void_p(table.data_ptr()),
                                         C.c_void_p(count.data_ptr()),
                                         C.c_void_p(work.data_ptr()), slots, self._stream()))
+        return table, count
+
+    def population_best_noalloc(self, table, count, slots=4096, dropped=None):
+        """tsf_population_best into caller-owned device buffers, with the
+        library's fixed working memory instead of a workspace: table (uint8,
+        >= slots entries of BEST_ENTRY_DTYPE), count (int32, 1), dropped
+        (optional int32, 1)."""
+        check(lib().tsf_population_best_noalloc(
+            C.byref(self.c()), C.c_void_p(table.data_ptr()), C.c_void_p(count.data_ptr()), slots,
+            C.c_void_p(dropped.data_ptr() if dropped is not None else None), self._stream()))
         return table, count
 
     def resize_into(self, out, table, count, base_seed, rnd, t_resize=ALWAYS, which=1,
