@@ -53,6 +53,13 @@ TSF_HD bool tern_neg_eq(T da, T sa, T db, T sb)
     return da == db && sa == (sb ^ db);
 }
 
+// three-way xor: one v_bitop3_b32 (truth table 0x96, odd parity) on gfx950
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TSF_XOR3(a, b, c) __builtin_amdgcn_bitop3_b32((a), (b), (c), 0x96)
+#else
+#define TSF_XOR3(a, b, c) ((a) ^ (b) ^ (c))
+#endif
+
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers
 // 0xD2511F53 / 0xCD9E8D57, key increments 0x9E3779B9 / 0xBB67AE85.
 struct Philox4 {
@@ -68,8 +75,8 @@ TSF_HD Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
     for (int round = 0; round < 10; ++round) {
         const uint64_t prod0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t prod1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t y0 = (uint32_t)(prod1 >> 32) ^ c1 ^ k0;
-        const uint32_t y2 = (uint32_t)(prod0 >> 32) ^ c3 ^ k1;
+        const uint32_t y0 = TSF_XOR3((uint32_t)(prod1 >> 32), c1, k0);
+        const uint32_t y2 = TSF_XOR3((uint32_t)(prod0 >> 32), c3, k1);
         c1 = (uint32_t)prod1;
         c3 = (uint32_t)prod0;
         c0 = y0;

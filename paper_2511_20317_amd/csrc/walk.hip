@@ -852,16 +852,20 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     if (s < 0)
         return tsf_fail(TSF_E_CAPACITY, "capacity %d needs more than 8 slots at %d lanes/walk",
                         b->capacity, g);
-    L.fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, strategy);
+    // factors of at most 16 entries: the indexed kernels keep each factor's
+    // digits and signs in one 32-bit LDS word
+    const bool pk = ix && !wide && b->max_len <= 16;
+    L.fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, pk ? 4 : strategy);
     if (!L.fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
     const size_t word = wide ? 8 : 4;
+    const size_t factor_bytes = pk ? 4 : 2 * word;
     const int walks_per_wave = 64 / g;
     // LDS stride per factor kind: capacity rounded up to even (to a multiple
     // of 4 for the indexed strategy, which reads four terms at a time)
     const int cap2 = ix ? (b->capacity + 3) & ~3 : b->capacity + (b->capacity & 1);
     // per walk: the terms, and for the indexed strategy 3 match masks per term
     // (rows of `capacity` masks, not padded)
-    const size_t per_walk = (size_t)cap2 * 6 * word + (ix ? (size_t)b->capacity * 3 * 8 : 0);
+    const size_t per_walk = (size_t)cap2 * 3 * factor_bytes + (ix ? (size_t)b->capacity * 3 * 8 : 0);
     L.lds = (size_t)wpb * walks_per_wave * per_walk;
     if (L.lds > 160 * 1024)
         return tsf_fail(TSF_E_CAPACITY, "%zu bytes of LDS per workgroup exceed 160 KiB", L.lds);

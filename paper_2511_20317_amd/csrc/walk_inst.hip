@@ -29,12 +29,19 @@ KernelFn pick_s(int s)
     }
 }
 
-// attempt-parallel kernels: indexed (at most 64 terms), or plain with
-// partner sets of s = 1 or 2 words (at most 64 or 128 terms)
+// attempt-parallel kernels: indexed (at most 64 terms; pk: factors of at
+// most 16 entries packed in one 32-bit LDS word), or plain with partner sets
+// of s = 1 or 2 words (at most 64 or 128 terms)
 template <int G>
-KernelFn pick_ap(bool ix, int s)
+KernelFn pick_ap(bool ix, int s, bool pk)
 {
-    if (ix) return s == 1 ? walk_kernel<G, 1, Word, kZ2, true, true> : nullptr;
+    if (ix) {
+        if (s != 1) return nullptr;
+        if constexpr (TSFK_WIDE == 0)
+            if (pk) return walk_kernel<G, 1, Word, kZ2, true, true, true>;
+        return pk ? nullptr : walk_kernel<G, 1, Word, kZ2, true, true>;
+    }
+    if (pk) return nullptr;
     switch (s) {
     case 1: return walk_kernel<G, 1, Word, kZ2, true, false>;
     case 2: return walk_kernel<G, 2, Word, kZ2, true, false>;
@@ -44,16 +51,17 @@ KernelFn pick_ap(bool ix, int s)
 
 #define TSF_CAT2(a, b, c) pick_kernel_w##a##_z##b##c
 #define TSF_CAT(a, b) TSF_CAT2(a, b, )
-// strategy: 1 attempt-parallel, 2 term-parallel, 3 indexed attempt-parallel
+// strategy: 1 attempt-parallel, 2 term-parallel, 3 indexed attempt-parallel,
+// 4 indexed attempt-parallel with packed factors
 KernelFn TSF_CAT(TSFK_WIDE, TSFK_Z2)(int g, int s, int strategy)
 {
-    if (strategy == 1 || strategy == 3) {
-        const bool ix = strategy == 3;
+    if (strategy == 1 || strategy == 3 || strategy == 4) {
+        const bool ix = strategy >= 3, pk = strategy == 4;
         switch (g) {
-        case 4: return pick_ap<4>(ix, s);
-        case 8: return pick_ap<8>(ix, s);
-        case 16: return pick_ap<16>(ix, s);
-        case 32: return pick_ap<32>(ix, s);
+        case 4: return pick_ap<4>(ix, s, pk);
+        case 8: return pick_ap<8>(ix, s, pk);
+        case 16: return pick_ap<16>(ix, s, pk);
+        case 32: return pick_ap<32>(ix, s, pk);
         default: return nullptr;
         }
     }

@@ -206,9 +206,13 @@ struct TermSet {
     }
 };
 
-template <int G, int S, typename T, bool Z2, bool AP, bool IX>
+template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK>
 struct Walker {
     static_assert(!IX || AP, "the match index extends the attempt-parallel strategy");
+    // PK: a factor of at most 16 entries is one 32-bit LDS word, digits in
+    // bits 0..15 and signs in bits 16..31 (indexed kernels only)
+    static_assert(!PK || (IX && sizeof(T) == 4), "packed factors: indexed kernels, 32-bit words");
+    static constexpr int kFW = PK ? 1 : 2;  // LDS words per factor
     // attempt-parallel kernels: S is the number of 64-bit words of a partner
     // set (capacity up to 64*S); the indexed strategy keeps one word
     static_assert(!AP || S == 1 || (S == 2 && !IX), "attempt-parallel partner sets of 1 or 2 words");
@@ -269,18 +273,37 @@ struct Walker {
         return (uint32_t)__shfl((int)v, gshift + lane);
     }
 
-    __device__ __forceinline__ int idx(int k, int X) const { return (X * cap2 + k) * 2; }
+    // The Philox block (iteration t, attempt att, domain dom) of this walk.
+    // The key passes through an empty asm statement, so the compiler cannot
+    // hoist the ten round keys of each half out of the iteration loop: they
+    // are recomputed (one add per round and half, which the three-way xor
+    // absorbs) instead of occupying twenty registers for the whole kernel.
+    __device__ __forceinline__ Philox4 draw(uint32_t att, uint32_t dom) const
+    {
+        uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+        asm volatile("" : "+v"(k0), "+v"(k1));
+        return philox4x32_10((uint32_t)(uint64_t)t, (uint32_t)((uint64_t)t >> 32), att, dom, k0, k1);
+    }
+
+    __device__ __forceinline__ int idx(int k, int X) const { return (X * cap2 + k) * kFW; }
+    __device__ __forceinline__ static TV<T> unpack(T w) { return TV<T>{w & 0xFFFFu, w >> 16}; }
+    __device__ __forceinline__ static T pack(TV<T> v) { return v.d | (v.s << 16); }
     __device__ __forceinline__ TV<T> ld(int k, int X) const
     {
         const T *q = lds + idx(k, X);
+        if constexpr (PK) return unpack(q[0]);
         return TV<T>{q[0], q[1]};
     }
     __device__ __forceinline__ void st(int k, int X, TV<T> v)
     {
         if (gl == 0) {
             T *q = lds + idx(k, X);
-            q[0] = v.d;
-            q[1] = v.s;
+            if constexpr (PK) {
+                q[0] = pack(v);
+            } else {
+                q[0] = v.d;
+                q[1] = v.s;
+            }
         }
     }
 
@@ -370,19 +393,35 @@ struct Walker {
     __device__ void refresh(int k1, int X1, TV<T> n1, uint64_t o1, int k2, int X2, TV<T> n2,
                             uint64_t o2)
     {
-        const int rend = wave_max_r();
-        for (int j0 = 0; j0 < rend; j0 += 4 * G) {
+        // PK: the factors are compared as packed words; p = the new value,
+        // q = the other accepted word (w negated: the signs flip where the
+        // digits are set), equal to p where no sign freedom applies
+        const T p1 = PK ? pack(n1) : 0, p2 = PK ? pack(n2) : 0;
+        const T q1 = (PK && !Z2 && X1 == 2) ? (p1 ^ (p1 << 16)) : p1;
+        const T q2 = (PK && !Z2 && X2 == 2) ? (p2 ^ (p2 << 16)) : p2;
+        // passes of 4G terms while some walk of the wavefront has terms left
+        for (int j0 = 0;; j0 += 4 * G) {
             const int jb = j0 + 4 * gl;
             if (jb < r) {
-                TV<T> f1[4], f2[4];
-                load4(jb, X1, f1);
-                load4(jb, X2, f2);
                 // nibbles of the four terms: relation now, then changed ones
                 uint32_t c1 = 0, c2 = 0;
+                if constexpr (PK) {
+                    const uint4 a1 = *reinterpret_cast<const uint4 *>(lds + idx(jb, X1));
+                    const uint4 a2 = *reinterpret_cast<const uint4 *>(lds + idx(jb, X2));
+                    const auto hit = [](T w, T p, T q) { return (w == p) | (w == q); };
+                    c1 = (hit(a1.x, p1, q1) ? 1u : 0u) | (hit(a1.y, p1, q1) ? 2u : 0u) |
+                         (hit(a1.z, p1, q1) ? 4u : 0u) | (hit(a1.w, p1, q1) ? 8u : 0u);
+                    c2 = (hit(a2.x, p2, q2) ? 1u : 0u) | (hit(a2.y, p2, q2) ? 2u : 0u) |
+                         (hit(a2.z, p2, q2) ? 4u : 0u) | (hit(a2.w, p2, q2) ? 8u : 0u);
+                } else {
+                    TV<T> f1[4], f2[4];
+                    load4(jb, X1, f1);
+                    load4(jb, X2, f2);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    c1 |= equiv(f1[e], n1, X1) ? 1u << e : 0u;
-                    c2 |= equiv(f2[e], n2, X2) ? 1u << e : 0u;
+                    for (int e = 0; e < 4; ++e) {
+                        c1 |= equiv(f1[e], n1, X1) ? 1u << e : 0u;
+                        c2 |= equiv(f2[e], n2, X2) ? 1u << e : 0u;
+                    }
                 }
                 const uint32_t live = (r - jb >= 4 ? 0xFu : (1u << (r - jb)) - 1u);
                 const uint32_t self1 = (uint32_t)(k1 - jb) < 4u ? 1u << (k1 - jb) : 0u;
@@ -400,6 +439,7 @@ struct Walker {
                     lds_xor(mk + X2 * capm + k2, 1ull << j);
                 }
             }
+            if (!__ballot(j0 + 4 * G < r)) break;
         }
         wave_lds_sync();
     }
@@ -480,8 +520,8 @@ struct Walker {
             }
         }
         if (h != last) {
-            for (int q = gl; q < 6; q += G) {
-                const int X = q >> 1, w = q & 1;
+            for (int q = gl; q < 3 * kFW; q += G) {
+                const int X = q / kFW, w = q % kFW;
                 lds[idx(h, X) + w] = lds[idx(last, X) + w];
             }
             if (tr0 == last) tr0 = h;
@@ -607,7 +647,7 @@ struct Walker {
             w1 = from_lane(pb.x[1], att);
             w2 = from_lane(pb.x[2], att);
         } else {
-            const Philox4 w = walk_block(seed, t, (uint32_t)att, 0);
+            const Philox4 w = draw((uint32_t)att, 0);
             w0 = w.x[0];
             w1 = w.x[1];
             w2 = w.x[2];
@@ -791,7 +831,7 @@ struct Walker {
                     w1 = pb.x[1];
                     w2 = pb.x[2];
                 } else {
-                    const Philox4 w = walk_block(seed, t, (uint32_t)att, 0);
+                    const Philox4 w = draw((uint32_t)att, 0);
                     w0 = w.x[0];
                     w1 = w.x[1];
                     w2 = w.x[2];
@@ -1094,7 +1134,7 @@ struct Walker {
     {
         if (r >= r_cap || r < 2) return false;
         for (int att = 0; att < 8; ++att) {
-            const Philox4 w = walk_block(seed, t, (uint32_t)att, 2);
+            const Philox4 w = draw((uint32_t)att, 2);
             const int i = (int)below(w.x[0], (uint32_t)r);
             int j = (int)below(w.x[1], (uint32_t)(r - 1));
             if (j >= i) ++j;
@@ -1155,7 +1195,16 @@ struct Walker {
     {
         for (int k = gl; k < rr; k += G)
 #pragma unroll
-            for (int x = 0; x < 6; ++x) lds[idx(k, x >> 1) + (x & 1)] = (T)src[k * 6 + x];
+            for (int X = 0; X < 3; ++X) {
+                const TV<T> v{(T)src[k * 6 + 2 * X], (T)src[k * 6 + 2 * X + 1]};
+                T *q = lds + idx(k, X);
+                if constexpr (PK) {
+                    q[0] = pack(v);
+                } else {
+                    q[0] = v.d;
+                    q[1] = v.s;
+                }
+            }
         wave_lds_sync();
         if constexpr (IX) {
             const int keep = r;
@@ -1170,10 +1219,11 @@ struct Walker {
         int c = 0;
         for (int k = gl; k < r; k += G)
 #pragma unroll
-            for (int x = 0; x < 6; ++x) {
-                const T v = lds[idx(k, x >> 1) + (x & 1)];
-                dst[k * 6 + x] = (uint64_t)v;
-                if ((x & 1) == 0) c += popc64((uint64_t)v);
+            for (int X = 0; X < 3; ++X) {
+                const TV<T> v = ld(k, X);
+                dst[k * 6 + 2 * X] = (uint64_t)v.d;
+                dst[k * 6 + 2 * X + 1] = (uint64_t)v.s;
+                c += popc64((uint64_t)v.d);
             }
         return group_sum(c);
     }
@@ -1218,7 +1268,7 @@ struct Walker {
         cnt[C_ITERS]++;
         // this iteration's draws: lane q < G-1 -> flip attempt q, lane G-1 -> gates
         const bool gate_lane = gl == G - 1;
-        pb = walk_block(seed, t, gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
+        pb = draw(gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
 #pragma unroll
         for (int q = 0; q < 3; ++q) gate[q] = from_lane(pb.x[q], G - 1);
         logging = a->log != nullptr && t <= a->log_cap;
@@ -1323,7 +1373,7 @@ struct Walker {
     __device__ void propose()
     {
         const bool gate_lane = gl == G - 1;
-        pb = walk_block(seed, t, gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
+        pb = draw(gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
         const int K = a->learn_k;
         uint32_t desc = ~0u;
         if (r >= 2) {
@@ -1400,12 +1450,14 @@ __device__ __forceinline__ int flen(int m, int n, int p, int X)
     return X == 0 ? m * n : X == 1 ? n * p : p * m;
 }
 
-// The indexed kernels with 32-bit masks and 8 or more lanes per walk are held
-// to 168 VGPRs, which keeps three wavefronts per SIMD (they fit it without
-// spilling; the 64-bit ones do not).
-template <int G, int S, typename T, bool Z2, bool AP, bool IX>
+// Register budgets: the packed indexed kernels (8 or more lanes per walk)
+// are held to 128 VGPRs, four wavefronts per SIMD, which their LDS also
+// allows at (3,3,3) (10,176 bytes per 8-walk wavefront, sixteen per CU); the
+// other indexed kernels with 32-bit masks to 168 VGPRs (three per SIMD, as
+// many as their LDS allows); the rest are not constrained.
+template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK = false>
 __global__ void __launch_bounds__(256) __attribute__((
-    amdgpu_waves_per_eu((IX && G >= 8 && sizeof(T) == 4) ? 3 : 1))) walk_kernel(KArgs a)
+    amdgpu_waves_per_eu(PK && G >= 8 ? 4 : (IX && G >= 8 && sizeof(T) == 4) ? 3 : 1))) walk_kernel(KArgs a)
 {
     extern __shared__ uint64_t smem_u64[];
     T *smem = reinterpret_cast<T *>(smem_u64);
@@ -1416,7 +1468,8 @@ __global__ void __launch_bounds__(256) __attribute__((
     const int64_t walk = ((int64_t)blockIdx.x * wpb + wave) * W + grp;
     if (walk >= a.n_walks) return;  // the whole group leaves together
 
-    Walker<G, S, T, Z2, AP, IX> wk;
+    using Wk = Walker<G, S, T, Z2, AP, IX, PK>;
+    Wk wk;
     wk.gl = lane % G;
     wk.gshift = grp * G;
     wk.cap2 = a.cap2;
@@ -1426,8 +1479,8 @@ __global__ void __launch_bounds__(256) __attribute__((
     // like the term rows, which keeps a wavefront's LDS small enough for one
     // more wavefront per CU at (3,3,3)
     const int slot = wave * W + grp;
-    wk.lds = smem + (size_t)slot * a.cap2 * 6;
-    wk.mk = reinterpret_cast<uint64_t *>(smem + (size_t)wpb * W * a.cap2 * 6) +
+    wk.lds = smem + (size_t)slot * a.cap2 * 3 * Wk::kFW;
+    wk.mk = reinterpret_cast<uint64_t *>(smem + (size_t)wpb * W * a.cap2 * 3 * Wk::kFW) +
             (size_t)slot * a.capm * 3;
     wk.a = &a;
     wk.walk = walk;
@@ -1437,7 +1490,7 @@ __global__ void __launch_bounds__(256) __attribute__((
     // a header that does not fit this kernel is never advanced
     const int lmax = max(flen(m, n, p, 0), max(flen(m, n, p, 1), flen(m, n, p, 2)));
     const bool sane = m >= 1 && n >= 1 && p >= 1 && lmax <= a.max_len &&
-                      lmax <= (int)(8 * sizeof(T)) && h->mode == (Z2 ? 1 : 0) &&
+                      lmax <= (PK ? 16 : (int)(8 * sizeof(T))) && h->mode == (Z2 ? 1 : 0) &&
                       h->r_cap <= a.cap && h->rank >= 0 && h->rank <= h->r_cap &&
                       h->best_rank >= 0 && h->best_rank <= a.cap && h->start_rank >= 0 &&
                       h->start_rank <= a.cap && (!AP || a.cap <= 64 * S) && (!IX || a.cap <= 64);
