@@ -184,6 +184,33 @@ struct TermSet {
         for (int q = 0; q < NW; ++q) c += __builtin_popcountll(w[q]);
         return c;
     }
+    // removes and returns the lowest member (the set is not empty)
+    __device__ __forceinline__ int pop()
+    {
+        if constexpr (NW == 1) {
+            const int k = __builtin_ctzll(w[0]);
+            w[0] &= w[0] - 1;
+            return k;
+        } else {
+            // the first non-empty word, chosen with selects (no indexed
+            // register access)
+            int k = -1;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const bool take = k < 0 && w[q] != 0;
+                k = take ? 64 * q + __builtin_ctzll(w[q]) : k;
+                w[q] = take ? w[q] & (w[q] - 1) : w[q];
+            }
+            return k;
+        }
+    }
+    // adds member k when `on`
+    __device__ __forceinline__ void set_if(int k, bool on)
+    {
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+            w[q] |= (on && (k >> 6) == q) ? 1ull << (k & 63) : 0ull;
+    }
     // the c-th (0-based) member in ascending order (the set has more than c)
     __device__ __forceinline__ int kth(int c) const
     {
@@ -287,6 +314,15 @@ struct Walker {
 
     __device__ __forceinline__ int idx(int k, int X) const { return (X * cap2 + k) * kFW; }
     __device__ __forceinline__ static TV<T> unpack(T w) { return TV<T>{w & 0xFFFFu, w >> 16}; }
+    // PK: the word held by every slot at or above the rank: signs without
+    // digits, which no factor (nor a factor with its signs flipped) is, so a
+    // comparison over a block of slots needs no mask of the live ones
+    static constexpr uint32_t kDead = 0xFFFF0000u;
+    // PK: store a packed word (lane 0 of the group)
+    __device__ __forceinline__ void stw(int k, int X, T w)
+    {
+        if (gl == 0) lds[idx(k, X)] = w;
+    }
     __device__ __forceinline__ static T pack(TV<T> v) { return v.d | (v.s << 16); }
     __device__ __forceinline__ TV<T> ld(int k, int X) const
     {
@@ -399,6 +435,7 @@ struct Walker {
         const T p1 = PK ? pack(n1) : 0, p2 = PK ? pack(n2) : 0;
         const T q1 = (PK && !Z2 && X1 == 2) ? (p1 ^ (p1 << 16)) : p1;
         const T q2 = (PK && !Z2 && X2 == 2) ? (p2 ^ (p2 << 16)) : p2;
+        const uint64_t b1 = 1ull << k1, b2 = 1ull << k2;
         // passes of 4G terms while some walk of the wavefront has terms left
         for (int j0 = 0;; j0 += 4 * G) {
             const int jb = j0 + 4 * gl;
@@ -423,19 +460,23 @@ struct Walker {
                         c2 |= equiv(f2[e], n2, X2) ? 1u << e : 0u;
                     }
                 }
-                const uint32_t live = (r - jb >= 4 ? 0xFu : (1u << (r - jb)) - 1u);
-                const uint32_t self1 = (uint32_t)(k1 - jb) < 4u ? 1u << (k1 - jb) : 0u;
-                const uint32_t self2 = (uint32_t)(k2 - jb) < 4u ? 1u << (k2 - jb) : 0u;
-                c1 = ((c1 & live & ~self1) ^ (uint32_t)(o1 >> jb)) & 0xFu;
-                c2 = ((c2 & live & ~self2) ^ (uint32_t)(o2 >> jb)) & 0xFu;
+                if constexpr (!PK) {
+                    // slots at or above the rank hold stale terms
+                    const uint32_t live = (r - jb >= 4 ? 0xFu : (1u << (r - jb)) - 1u);
+                    c1 &= live;
+                    c2 &= live;
+                }
+                // changed relations; a term is never in its own mask
+                c1 = (c1 ^ (uint32_t)(o1 >> jb)) & ~(uint32_t)(b1 >> jb) & 0xFu;
+                c2 = (c2 ^ (uint32_t)(o2 >> jb)) & ~(uint32_t)(b2 >> jb) & 0xFu;
                 for (; c1; c1 &= c1 - 1) {
                     const int j = jb + __builtin_ctz(c1);
-                    lds_xor(mk + X1 * capm + j, 1ull << k1);
+                    lds_xor(mk + X1 * capm + j, b1);
                     lds_xor(mk + X1 * capm + k1, 1ull << j);
                 }
                 for (; c2; c2 &= c2 - 1) {
                     const int j = jb + __builtin_ctz(c2);
-                    lds_xor(mk + X2 * capm + j, 1ull << k2);
+                    lds_xor(mk + X2 * capm + j, b2);
                     lds_xor(mk + X2 * capm + k2, 1ull << j);
                 }
             }
@@ -519,11 +560,19 @@ struct Walker {
                 }
             }
         }
-        if (h != last) {
+        if constexpr (PK) {
+            // slot `last` becomes a dead slot
+            if (gl < 3) {
+                if (h != last) lds[idx(h, gl)] = lds[idx(last, gl)];
+                lds[idx(last, gl)] = kDead;
+            }
+        } else if (h != last) {
             for (int q = gl; q < 3 * kFW; q += G) {
                 const int X = q / kFW, w = q % kFW;
                 lds[idx(h, X) + w] = lds[idx(last, X) + w];
             }
+        }
+        if (h != last) {
             if (tr0 == last) tr0 = h;
             if (tr1 == last) tr1 = h;
         }
@@ -576,10 +625,34 @@ struct Walker {
     {
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
         const int Y = role ? B : A, Z = role ? A : B;
-        // every factor the flip reads is read up front (one round of reads)
-        const TV<T> xi = ld(i, X), yi = ld(i, Y), zi0 = ld(i, Z);
-        const TV<T> xj = ld(j, X), yj = ld(j, Y), zj0 = ld(j, Z);
-        const int sg = rel(xi, xj, X);
+        // every factor the flip reads is read up front (one round of reads);
+        // PK: the sign is a comparison of packed words, and a w whose signs
+        // flip is flipped as a packed word
+        TV<T> xi, yi, zi0, xj, yj, zj0;
+        T wxi = 0, wzi = 0, wxj = 0, wyj = 0;
+        int sg;
+        if constexpr (PK) {
+            wxi = lds[idx(i, X)];
+            wzi = lds[idx(i, Z)];
+            wxj = lds[idx(j, X)];
+            wyj = lds[idx(j, Y)];
+            const T wyi = lds[idx(i, Y)], wzj = lds[idx(j, Z)];
+            xi = unpack(wxi);
+            yi = unpack(wyi);
+            zi0 = unpack(wzi);
+            xj = unpack(wxj);
+            yj = unpack(wyj);
+            zj0 = unpack(wzj);
+            sg = (Z2 || wxi == wxj) ? 1 : -1;
+        } else {
+            xi = ld(i, X);
+            yi = ld(i, Y);
+            zi0 = ld(i, Z);
+            xj = ld(j, X);
+            yj = ld(j, Y);
+            zj0 = ld(j, Z);
+            sg = rel(xi, xj, X);
+        }
         if (logging && gl == 0) {
             tsf_flip_log *lg = a->log + (size_t)walk * a->log_cap + (t - 1);
             const TV<T> fv[6] = {xi, yi, zi0, xj, yj, zj0};
@@ -604,15 +677,25 @@ struct Walker {
             // y is not w; w of term j is x_j or y_j when z is not w)
             if (Y != 2 && (ny.s & ny.d & (~ny.d + 1))) {
                 ny.s ^= ny.d;
-                TV<T> w = X == 2 ? xi : zi0;
-                w.s ^= w.d;
-                st(i, 2, w);
+                if constexpr (PK) {
+                    const T w = X == 2 ? wxi : wzi;
+                    stw(i, 2, w ^ (w << 16));
+                } else {
+                    TV<T> w = X == 2 ? xi : zi0;
+                    w.s ^= w.d;
+                    st(i, 2, w);
+                }
             }
             if (Z != 2 && (nz.s & nz.d & (~nz.d + 1))) {
                 nz.s ^= nz.d;
-                TV<T> w = X == 2 ? xj : yj;
-                w.s ^= w.d;
-                st(j, 2, w);
+                if constexpr (PK) {
+                    const T w = X == 2 ? wxj : wyj;
+                    stw(j, 2, w ^ (w << 16));
+                } else {
+                    TV<T> w = X == 2 ? xj : yj;
+                    w.s ^= w.d;
+                    st(j, 2, w);
+                }
             }
         }
         if constexpr (IX) {
@@ -716,76 +799,123 @@ struct Walker {
     }
 
     // ------------------------------------------------------------------ AP
-    // Partners of (i, X) for this lane alone, over all r <= 64*NW terms:
-    // member k of m0/m1 when (k, role 0/1) is a valid flip partner.  The
-    // match scan runs to the batch capacity (a wave-uniform bound, so the loop
-    // counter and the bit constants stay scalar; 32 terms per partial mask)
-    // and drops terms >= r.
-    __device__ void candidates_ap(int i, int X, PSet &m0, PSet &m1) const
+    // Partners of attempt (i, X) for this lane (when `active`), over all
+    // r <= 64*NW terms: member k of m0/m1 when (k, role 0/1) is a valid flip
+    // partner.  The match scan runs to the batch capacity (a wave-uniform
+    // bound, so the loop counter and the bit constants stay scalar; 32 terms
+    // per partial mask) and drops terms >= r.  Then the matches are tested
+    // one at a time.  (Stopping the lanes after the first lane of the group
+    // that has a partner measured slower: 10% with a group ballot after
+    // every match, 2% with one ballot after the first.)
+    __device__ void candidates_ap(bool active, int i, int X, PSet &m0, PSet &m1) const
     {
-        const TV<T> xi = ld(i, X);
-        PSet match;
-        if constexpr (IX) {
-            match.w[0] = mk[X * capm + i];
-        } else {
-            const T nsi = (!Z2 && X == 2) ? (xi.s ^ xi.d) : xi.s;  // accepted signs besides xi.s
-            const T *col = lds + idx(0, X);
-            const int kend = scan_end;  // even, wave-uniform
-            uint32_t part[2 * NW];
-            int k = 0;
-#pragma unroll
-            for (int c = 0; c < 2 * NW; ++c) {
-                part[c] = 0;
-                const int kc = kend < 32 * (c + 1) ? kend : 32 * (c + 1);
-                // four terms per step while four remain, then two
-                for (; k + 2 < kc; k += 4) {
-                    const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2],
-                            s1 = col[2 * k + 3], d2 = col[2 * k + 4], s2 = col[2 * k + 5],
-                            d3 = col[2 * k + 6], s3 = col[2 * k + 7];
-                    const int sh = k - 32 * c;
-                    part[c] |= ((d0 == xi.d) & ((s0 == xi.s) | (s0 == nsi)) ? 1u : 0u) << sh;
-                    part[c] |= ((d1 == xi.d) & ((s1 == xi.s) | (s1 == nsi)) ? 2u : 0u) << sh;
-                    part[c] |= ((d2 == xi.d) & ((s2 == xi.s) | (s2 == nsi)) ? 4u : 0u) << sh;
-                    part[c] |= ((d3 == xi.d) & ((s3 == xi.s) | (s3 == nsi)) ? 8u : 0u) << sh;
-                }
-                if (k < kc) {
-                    const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2],
-                            s1 = col[2 * k + 3];
-                    const uint32_t b0 = 1u << (k - 32 * c), b1 = 2u << (k - 32 * c);
-                    part[c] |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
-                    part[c] |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
-                    k += 2;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                const int lo = 64 * q;
-                const uint64_t live = r - lo >= 64 ? ~0ull : (r > lo ? (1ull << (r - lo)) - 1 : 0ull);
-                const uint64_t self = (i >> 6) == q ? 1ull << (i & 63) : 0ull;
-                match.w[q] = (((uint64_t)part[2 * q + 1] << 32) | part[2 * q]) & live & ~self;
-            }
-        }
         m0.clear();
         m1.clear();
+        PSet match;
+        match.clear();
+        TV<T> xi{0, 0};
+        if (active) {
+            xi = ld(i, X);
+            if constexpr (IX) {
+                match.w[0] = mk[X * capm + i];
+            } else {
+                const T nsi = (!Z2 && X == 2) ? (xi.s ^ xi.d) : xi.s;  // accepted signs besides xi.s
+                const T *col = lds + idx(0, X);
+                const int kend = scan_end;  // even, wave-uniform
+                uint32_t part[2 * NW];
+                int k = 0;
+#pragma unroll
+                for (int c = 0; c < 2 * NW; ++c) {
+                    part[c] = 0;
+                    const int kc = kend < 32 * (c + 1) ? kend : 32 * (c + 1);
+                    // four terms per step while four remain, then two
+                    for (; k + 2 < kc; k += 4) {
+                        const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2],
+                                s1 = col[2 * k + 3], d2 = col[2 * k + 4], s2 = col[2 * k + 5],
+                                d3 = col[2 * k + 6], s3 = col[2 * k + 7];
+                        const int sh = k - 32 * c;
+                        part[c] |= ((d0 == xi.d) & ((s0 == xi.s) | (s0 == nsi)) ? 1u : 0u) << sh;
+                        part[c] |= ((d1 == xi.d) & ((s1 == xi.s) | (s1 == nsi)) ? 2u : 0u) << sh;
+                        part[c] |= ((d2 == xi.d) & ((s2 == xi.s) | (s2 == nsi)) ? 4u : 0u) << sh;
+                        part[c] |= ((d3 == xi.d) & ((s3 == xi.s) | (s3 == nsi)) ? 8u : 0u) << sh;
+                    }
+                    if (k < kc) {
+                        const T d0 = col[2 * k], s0 = col[2 * k + 1], d1 = col[2 * k + 2],
+                                s1 = col[2 * k + 3];
+                        const uint32_t b0 = 1u << (k - 32 * c), b1 = 2u << (k - 32 * c);
+                        part[c] |= (d0 == xi.d && (s0 == xi.s || s0 == nsi)) ? b0 : 0u;
+                        part[c] |= (d1 == xi.d && (s1 == xi.s || s1 == nsi)) ? b1 : 0u;
+                        k += 2;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const int lo = 64 * q;
+                    const uint64_t live = r - lo >= 64 ? ~0ull : (r > lo ? (1ull << (r - lo)) - 1 : 0ull);
+                    const uint64_t self = (i >> 6) == q ? 1ull << (i & 63) : 0ull;
+                    match.w[q] = (((uint64_t)part[2 * q + 1] << 32) | part[2 * q]) & live & ~self;
+                }
+            }
+        }
         if (!match.any()) return;
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
-        const TV<T> Ai = ld(i, A), Bi = ld(i, B);
-#pragma unroll
-        for (int q = 0; q < NW; ++q) {
-            for (uint64_t mm = match.w[q]; mm; mm &= mm - 1) {
-                const int kb = __builtin_ctzll(mm);
-                const int kk = 64 * q + kb;
+        // the factors of term i that the tests read (packed words for PK)
+        T wx = 0, wa = 0, wb = 0;
+        TV<T> Ai{0, 0}, Bi{0, 0};
+        if constexpr (PK) {
+            wx = lds[idx(i, X)];
+            wa = lds[idx(i, A)];
+            wb = lds[idx(i, B)];
+        } else {
+            Ai = ld(i, A);
+            Bi = ld(i, B);
+        }
+        do {
+            const int kk = match.pop();
+            bool v0, v1;
+            if constexpr (PK) {
+                roles_packed(wx, wa, wb, lds[idx(kk, X)], lds[idx(kk, A)], lds[idx(kk, B)],
+                             v0, v1);
+            } else {
                 const int sg = (Z2 || ld(kk, X).s == xi.s) ? 1 : -1;
                 const TV<T> Ak = ld(kk, A), Bk = ld(kk, B);
                 TV<T> o1, o2;
                 const bool a1 = axpy(sg, Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
                 const bool a2 = axpy(sg, Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
-                // a valid sum or difference is zero exactly when the supports
-                // agree; the additions objective admits no such flip
+                // a valid sum or difference is zero exactly when the
+                // supports agree; the additions objective admits no such
+                // flip
                 const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
-                m0.w[q] |= (uint64_t)(a1 && b1 && keep) << kb;
-                m1.w[q] |= (uint64_t)(a2 && b2 && keep) << kb;
+                v0 = a1 && b1 && keep;
+                v1 = a2 && b2 && keep;
             }
+            m0.set_if(kk, v0);
+            m1.set_if(kk, v1);
+        } while (match.any());
+    }
+
+    // The validity tests of candidates_ap on packed words (digits in bits
+    // 0..15, signs in 16..31): x, a, b = factors X, A, B of term i; xk, ak, bk
+    // those of term k.  Where both factors are non-zero, equal signs make a
+    // sum leave the set and different signs a difference (Sec. 3.5.2).
+    // Role 0 needs a_i + sigma a_k and b_k - b_i, role 1 b_i + sigma b_k and
+    // a_k - a_i; sigma = +1 unless w_k = -w_i.
+    __device__ __forceinline__ void roles_packed(T x, T a, T b, T xk, T ak, T bk, bool &v0,
+                                                 bool &v1) const
+    {
+        const T xa = a ^ ak, xb = b ^ bk;
+        bool keep = true;
+        if (additions) keep = ((xa & 0xFFFFu) != 0) & ((xb & 0xFFFFu) != 0);
+        if constexpr (Z2) {
+            v0 = v1 = keep;
+        } else {
+            const T ya = xa >> 16, yb = xb >> 16;
+            const T ba = a & ak & 0xFFFFu, bb = b & bk & 0xFFFFu;
+            const bool da = (ba & ya) == 0, db = (bb & yb) == 0;    // no opposite signs
+            const bool sa = (ba & ~ya) == 0, sb = (bb & ~yb) == 0;  // no equal signs
+            const bool pos = xk == x;
+            v0 = (pos ? sa : da) & db & keep;
+            v1 = (pos ? sb : db) & da & keep;
         }
     }
 
@@ -841,7 +971,7 @@ struct Walker {
                 PSet m0, m1;
                 m0.clear();
                 m1.clear();
-                if (active) candidates_ap(i, X, m0, m1);
+                candidates_ap(active, i, X, m0, m1);
                 const int n0 = m0.count(), n = n0 + m1.count();
                 const uint64_t ok = gballot(n > 0);
                 if (ok) {
@@ -928,7 +1058,7 @@ struct Walker {
             PSet m0, m1;
             m0.clear();
             m1.clear();
-            if (q < npairs) candidates_ap(i, X, m0, m1);
+            candidates_ap(q < npairs, i, X, m0, m1);
             const int n0 = m0.count(), n = n0 + m1.count();
             const uint64_t ok = gballot(n > 0);
             if (ok) {
@@ -1205,6 +1335,10 @@ struct Walker {
                     q[1] = v.s;
                 }
             }
+        if constexpr (PK)
+            for (int k = rr + gl; k < cap2; k += G)
+#pragma unroll
+                for (int X = 0; X < 3; ++X) lds[idx(k, X)] = kDead;
         wave_lds_sync();
         if constexpr (IX) {
             const int keep = r;
@@ -1265,7 +1399,6 @@ struct Walker {
 
     __device__ void begin_iteration()
     {
-        cnt[C_ITERS]++;
         // this iteration's draws: lane q < G-1 -> flip attempt q, lane G-1 -> gates
         const bool gate_lane = gl == G - 1;
         pb = draw(gate_lane ? 0u : (uint32_t)gl, gate_lane ? 1u : 0u);
@@ -1286,7 +1419,6 @@ struct Walker {
             cnt[C_DEAD_ENDS]++;
             grow = !additions;
         } else {
-            cnt[C_FLIPS]++;
             int tr0 = fi, tr1 = fj;
             // gates: block (t, 0, 1), drawn by the last lane of the group
             const uint32_t g0 = gate[0];
@@ -1383,7 +1515,7 @@ struct Walker {
             PSet m0, m1;
             m0.clear();
             m1.clear();
-            if (gl < K) candidates_ap(i, X, m0, m1);
+            candidates_ap(gl < K, i, X, m0, m1);
             const int n0 = m0.count(), n = n0 + m1.count();
             if (n > 0) {
                 int c = (int)below(pb.x[2], (uint32_t)n);
@@ -1510,6 +1642,7 @@ __global__ void __launch_bounds__(256) __attribute__((
     wk.target = h->target_rank;
     wk.n_rec = h->n_rec;
     wk.t = h->t;
+    const int64_t t_first = wk.t;
     wk.plateau_start = h->plateau_start;
 #pragma unroll
     for (int c = 0; c < C_NUM; ++c) wk.cnt[c] = 0;
@@ -1552,6 +1685,9 @@ __global__ void __launch_bounds__(256) __attribute__((
         h->n_rec = wk.n_rec;
         h->t = wk.t;
         h->plateau_start = wk.plateau_start;
+        // every iteration of this call is a flip or a dead end
+        wk.cnt[C_ITERS] = (uint32_t)(wk.t - t_first);
+        wk.cnt[C_FLIPS] = wk.cnt[C_ITERS] - wk.cnt[C_DEAD_ENDS];
         for (int c = 0; c < C_NUM; ++c) h->counters[c] += wk.cnt[c];
     }
 }
