@@ -9,6 +9,11 @@ the GPU Brent check of every walk's best scheme; the 1e6-iteration budget is
 split evenly over the timed steps (--steps 20: 5e4 iterations per launch), so
 every timed launch does work.
 
+After the timed steps (outside the timed region): the time to rank 23 in
+rounds of 1,000 iterations on a fresh batch, the learned proposal against
+uniform proposals (learned_vs_uniform; --no-learned skips it), and the CPU
+oracle on a bounded sample (cpu_baseline; --no-cpu skips it).
+
 Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
 build measures one GPU.
 """
@@ -87,40 +92,81 @@ def cpu_baseline(n_walks=512, iters=100000, threads=None):
 
 
 def learned_vs_uniform(ctx, args):
-    """Train the proposal network on logged uniform (3,3,3) walks, then compare
-    learned and uniform proposals at equal wall time on R runs over disjoint
-    seed blocks: medians of the time and of the iterations to each rank."""
+    """The learned proposal: a network (512 -> 256 -> 256 -> 1, bf16 on the
+    matrix cores) scores the candidates of an iteration's attempts and the
+    walk applies the best scored one.  Trained by the GPU kernels on logged
+    flips of uniform (2,2,2) and (3,3,3) walks with 20-flip labels (a quarter
+    of every minibatch drawn from the rare positives); reported:
+    held-out AUC before and after training; what it gains per iteration (the
+    share of walks that reach each rank within a fixed number of iterations,
+    for the trained network, an untrained network choosing among the same
+    candidates, and uniform proposals, over seed blocks); and learned against
+    uniform proposals at equal wall time on (3,3,3) (and (4,4,4) with
+    --learned-444): medians over R disjoint seed blocks of the time to each
+    rank of the ladder (inf where a run does not reach it)."""
     import torch
     from paper_2511_20317_amd import learn, tsf
-    s333 = tsf.init_scheme(3, 3, 3)
+    s222, s333 = tsf.init_scheme(2, 2, 2), tsf.init_scheme(3, 3, 3)
     t0 = time.perf_counter()
-    rec, idx, lab = learn.collect(ctx, s333, args.learn_walks, args.learn_iters, 35,
-                                  base_seed=10 ** 7)
+    rec, idx, lab = learn.training_set(ctx, n222=2 * args.learn_walks, n333=args.learn_walks,
+                                       n_iters=args.learn_iters, base_seed=10 ** 7)
+    held = {"2,2,2": learn.collect(ctx, s222, 1024, args.learn_iters, 16, base_seed=2 * 10 ** 7),
+            "3,3,3": learn.collect(ctx, s333, 512, args.learn_iters, 35, base_seed=3 * 10 ** 7)}
     t_collect = time.perf_counter() - t0
-    net = tsf.Mlp()
-    rng = np.random.default_rng(0)
-    net.set_params(rng.standard_normal((512, 256)) * np.sqrt(2 / 64), np.zeros(256),
-                   rng.standard_normal((256, 256)) * np.sqrt(2 / 256), np.zeros(256),
-                   rng.standard_normal(256) * np.sqrt(1 / 256), np.zeros(1))
-    # held-out flips: walks of another seed block
-    held, hidx, hlab = learn.collect(ctx, s333, max(args.learn_walks // 4, 1), args.learn_iters,
-                                     35, base_seed=2 * 10 ** 7)
-    ev0 = learn.evaluate(net, held, hidx, hlab)
+
+    def fresh_net(seed):
+        net = tsf.Mlp()
+        rng = np.random.default_rng(seed)
+        net.set_params(rng.standard_normal((512, 256)) * np.sqrt(2 / 64), np.zeros(256),
+                       rng.standard_normal((256, 256)) * np.sqrt(2 / 256), np.zeros(256),
+                       rng.standard_normal(256) * np.sqrt(1 / 256), np.zeros(1))
+        return net
+
+    net = fresh_net(0)
+    ev0 = {k: learn.evaluate(net, *v) for k, v in held.items()}
     t0 = time.perf_counter()
     hist = learn.train(net, rec, idx, lab, args.learn_steps, batch=4096, lr=1e-3,
-                       log_every=max(args.learn_steps // 5, 1))
+                       log_every=max(args.learn_steps // 5, 1), pos_share=0.25)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    ev = learn.evaluate(net, held, hidx, hlab)
-    p = float(hlab.mean())
-    constant_loss = -(p * np.log(p) + (1 - p) * np.log(1 - p)) if 0 < p < 1 else 0.0
+    ev = {k: learn.evaluate(net, *v) for k, v in held.items()}
+    n_logged = int(idx.size)
     del rec, held
-    out = {"train": {"logged_iterations": int(idx.size), "positive_rate": float(lab.mean()),
-                     "collect_s": t_collect, "train_s": t_train, "steps": args.learn_steps,
-                     "batch": 4096, "loss_history": hist, "held_out_before": ev0,
-                     "held_out_after": ev, "constant_predictor_loss": constant_loss}}
+    out = {"train": {"labelled_flips": n_logged, "positive_rate": float(lab.mean()),
+                     "label_window": learn.LABEL_WINDOW, "collect_s": t_collect,
+                     "train_s": t_train, "steps": args.learn_steps, "batch": 4096,
+                     "positive_share_of_minibatch": 0.25,
+                     "loss_history": hist, "held_out_before": ev0, "held_out_after": ev}}
+    print("learned: trained, held-out AUC %s" % {k: round(v["auc"], 3) for k, v in ev.items()},
+          file=sys.stderr, flush=True)
+    # per iteration: the same iterations for every proposal kind
+    untrained = fresh_net(7)
+    per_it = {}
+    for key, s, r_cap, iters, ladder in (("2,2,2", s222, 16, 3000, (7,)),
+                                         ("3,3,3", s333, 35, 20000, (26, 25, 24))):
+        acc = {}
+        for kind, nn in (("trained", net), ("untrained", untrained), ("uniform", None)):
+            fr = {str(k): [] for k in ladder}
+            walls = []
+            for blk in range(3):
+                r = learn.reach(ctx, s, r_cap, 2048, iters, ladder, base_seed=(blk + 1) << 21,
+                                net=nn)
+                walls.append(r["wall_s"])
+                for k in ladder:
+                    fr[str(k)].append(r["ranks"][str(k)]["fraction"])
+            acc[kind] = {"share_reaching": {k: float(np.mean(v)) for k, v in fr.items()},
+                         "wall_s_per_run": float(np.mean(walls))}
+        per_it[key] = {"walks": 2048, "iterations": iters, "seed_blocks": 3, "by_proposal": acc}
+        print("learned: per-iteration %s %s" % (key, {k: v["share_reaching"]
+                                                      for k, v in acc.items()}),
+              file=sys.stderr, flush=True)
+    out["per_iteration"] = per_it
+    # equal wall time
     results = {}
-    for fmt, r_cap, ladder in [((3, 3, 3), 35, (26, 25, 24, 23)), ((4, 4, 4), 64, (63, 62, 61, 60))]:
+    cases = [((3, 3, 3), 35, (26, 25, 24, 23))]
+    if args.learned_444:
+        cases.append(((4, 4, 4), 64, (63, 62, 61, 60)))
+    for fmt, r_cap, ladder in cases:
         s = tsf.init_scheme(*fmt)
         runs = {"uniform": [], "learned": []}
         for rep in range(args.ab_runs):
@@ -129,9 +175,6 @@ def learned_vs_uniform(ctx, args):
                 res = learn.time_to_ranks(ctx, s, args.ab_walks, r_cap, ladder, args.ab_seconds,
                                           seed, net=net if mode == "learned" else None)
                 runs[mode].append(res)
-                print("%s %s run %d: best %d, %.2f s, %d iterations" %
-                      (fmt, mode, rep, res["best_rank"], res["wall_s"], res["iterations"]),
-                      file=sys.stderr, flush=True)
         summ = {}
         for mode, rs in runs.items():
             summ[mode] = {
@@ -143,8 +186,12 @@ def learned_vs_uniform(ctx, args):
                 "best_rank_median": float(np.median([r["best_rank"] for r in rs])),
             }
         results["%d,%d,%d" % fmt] = summ
-    out["ab"] = results
-    out["ab_setup"] = {"runs": args.ab_runs, "walks": args.ab_walks, "wall_s": args.ab_seconds}
+        print("learned: equal wall time %s %s" % (fmt, {m: v["median_time_to_rank_s"]
+                                                        for m, v in summ.items()}),
+              file=sys.stderr, flush=True)
+    out["equal_wall_time"] = results
+    out["equal_wall_time_setup"] = {"runs": args.ab_runs, "walks": args.ab_walks,
+                                    "wall_s": args.ab_seconds}
     return out
 
 
@@ -467,14 +514,18 @@ def main():
                              "learned-walk"],
                     help="333: the (3,3,3) benchmark; mixed / large / additions: the other "
                          "workloads")
-    ap.add_argument("--learned", action="store_true",
-                    help="also train the proposal network and compare it with uniform proposals")
-    ap.add_argument("--learn-walks", type=int, default=2048)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training the proposal network and its comparison with uniform "
+                         "proposals")
+    ap.add_argument("--learned-444", action="store_true",
+                    help="also compare learned and uniform proposals at equal wall time on (4,4,4)")
+    ap.add_argument("--learn-walks", type=int, default=2048,
+                    help="(3,3,3) walks logged for training (twice as many (2,2,2) walks)")
     ap.add_argument("--learn-iters", type=int, default=6000)
-    ap.add_argument("--learn-steps", type=int, default=2000)
+    ap.add_argument("--learn-steps", type=int, default=1500)
     ap.add_argument("--ab-runs", type=int, default=9)
     ap.add_argument("--ab-walks", type=int, default=4096)
-    ap.add_argument("--ab-seconds", type=float, default=4.0)
+    ap.add_argument("--ab-seconds", type=float, default=1.5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the walks shard by walk id with no "
@@ -655,7 +706,7 @@ def main():
         "best_schemes_failing_brent": bad_total,
         "learned_vs_uniform": None,
     }
-    if args.learned:
+    if not args.no_learned:
         out["learned_vs_uniform"] = learned_vs_uniform(ctx, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_walks, args.cpu_iters)
