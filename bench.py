@@ -322,7 +322,7 @@ def run_additions(ctx, args):
     batch = tsf.WalkBatch.empty(n, focus.capacity, tsf.TSF_TERNARY, max_len=9, rec_cap=32)
     batch.meta_from(focus, 1, np.zeros(n), np.zeros(n), np.zeros(n), r_cap_extra=0)
     batch.init(ctx)
-    batch.hdr.view(torch.int32).view(n, 40)[:, 5] = 0   # target additions: none
+    batch.hdr.view(torch.int32).view(n, tsf.HEADER_I32)[:, 5] = 0   # target additions: none
     h0 = batch.headers()
     start_add = h0["best_nnz"] - 2 * h0["start_rank"] - 9
     prm = tsf.walk_params(base_seed=1 << 40, max_iters=10 ** 9, plateau=50000,
@@ -466,7 +466,7 @@ def time_to_rank_fine(ctx, args, target=23, round_iters=1000, limit_s=60.0):
     b = tsf.WalkBatch([(tsf.init_scheme(3, 3, 3), args.walks, 35, target)], rec_cap=32)
     prm = tsf.walk_params(base_seed=0, max_iters=1000000, plateau=50000)
     b.init(ctx)
-    best_col = b.hdr.view(torch.int32).view(args.walks, 40)[:, 7]
+    best_col = b.hdr.view(torch.int32).view(args.walks, tsf.HEADER_I32)[:, 7]
     ladder, done = {}, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -593,8 +593,8 @@ def main():
 
     batch.init(ctx)
     hdr0 = torch.cuda.synchronize() or batch.headers()
-    i32 = batch.hdr.view(torch.int32).view(args.walks, 40)
-    i64 = batch.hdr.view(torch.int64).view(args.walks, 20)
+    i32 = batch.hdr.view(torch.int32).view(args.walks, tsf.HEADER_I32)
+    i64 = batch.hdr.view(torch.int64).view(args.walks, tsf.HEADER_I32 // 2)
     best_col, rank_col, iters_col, flips_col = i32[:, 7], i32[:, 6], i64[:, 8], i64[:, 9]
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]

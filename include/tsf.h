@@ -232,7 +232,7 @@ typedef struct {
 #define TSF_OBJ_RANK 0
 #define TSF_OBJ_ADDITIONS 1
 
-/* Per-walk state header (device memory, one per walk, 160 bytes). */
+/* Per-walk state header (device memory, one per walk, 176 bytes). */
 typedef struct {
     int32_t m, n, p, mode;     /* the walk's format and coefficient set           */
     int32_t r_cap;             /* expand is refused at this rank (<= capacity)    */
@@ -241,7 +241,9 @@ typedef struct {
     int32_t best_rank;         /* rank of the best scheme                         */
     int32_t start_rank;        /* rank of the start scheme                        */
     int32_t done;              /* 1 once the target was reached; -1 header does
-                                  not fit the batch; -2 invalid start scheme      */
+                                  not fit the batch; -2 invalid start scheme;
+                                  -3 resumed with other walk parameters than the
+                                  walk was run with (TSF_E_STATE)               */
     int32_t n_rec;             /* strict improvements so far (records kept up to
                                   the batch's rec_cap)                            */
     int32_t best_nnz;          /* non-zero coefficients of the best scheme        */
@@ -250,6 +252,9 @@ typedef struct {
     int64_t counters[12];      /* iters, flips, attempts, fallbacks, dead_ends,
                                   zero_removed, merges, expands, expand_fails,
                                   restarts, eq_accepts, improvements              */
+    uint64_t params_hash;      /* tsf_params_hash of the parameters of the walk's
+                                  last tsf_walk call; 0 after tsf_walk_init       */
+    uint64_t reserved;
 } tsf_walk_header;
 
 /* One strict improvement of a walk's best rank (TSF_OBJ_ADDITIONS: of its
@@ -364,12 +369,31 @@ tsf_status tsf_walk_init(tsf_ctx *ctx, const tsf_walk_batch *b, void *hip_stream
  * not depend on the launch configuration or on how iterations are split
  * into calls.
  * Asynchronous on `hip_stream`; `launch` may be NULL (library choice).
- * The host validates the batch shape against the chosen kernel; the per-walk
- * headers are device data and are trusted to be what tsf_walk_init and
- * earlier tsf_walk calls left.  Errors: TSF_E_ARG, TSF_E_CAPACITY,
+ * The host validates the batch shape against the chosen kernel.  Resuming:
+ * a walk's header keeps the hash of the parameters it was last run with
+ * (tsf_params_hash; everything but n_iters, which may differ per call); a
+ * walk whose stored hash is neither 0 (fresh from tsf_walk_init) nor the
+ * hash of `prm` is not advanced and gets done = -3, which tsf_walk_check
+ * reports as TSF_E_STATE.  Errors: TSF_E_ARG, TSF_E_CAPACITY,
  * TSF_E_DEVICE. */
 tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
                     int64_t n_iters, const tsf_launch *launch, void *hip_stream);
+
+/* FNV-1a hash (64-bit) of the walk parameters that a resumed walk must keep:
+ * base_seed, first_walk_id, max_iters, plateau, t_eq, t_reduce, t_expand,
+ * flip_tries, restart_from_best, objective (each as its little-endian bytes,
+ * in that order); never 0 (a hash of 0 is replaced by 1).  Host only. */
+uint64_t tsf_params_hash(const tsf_walk_params *prm);
+
+/* Resume check of a batch on the host (synchronous, for callers that resume
+ * batches from checkpoints): `hdr` is a host copy of the batch's n_walks
+ * headers.  Counts the walks whose stored parameter hash is neither 0 nor
+ * tsf_params_hash(prm), or that a walk call already refused (done = -3),
+ * into *n_mismatched (may be NULL).  Returns TSF_E_STATE if there is any,
+ * TSF_E_ARG on null arguments or n_walks < 0, else TSF_OK.  Reads only the
+ * headers; caller-owned memory. */
+tsf_status tsf_walk_check(const tsf_walk_params *prm, const tsf_walk_header *hdr,
+                          int32_t n_walks, int32_t *n_mismatched);
 
 /* Exact Brent verification (Eq. 1, C^T form of Sec. 3.1) on the GPU of one
  * scheme per walk of the batch: which = 0 checks cur (rank hdr[w].rank),

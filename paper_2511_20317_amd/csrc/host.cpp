@@ -536,3 +536,49 @@ tsf_status tsf_unpack(const uint64_t *packed, const tsf_dims *d, tsf_scheme *out
 }  // extern "C"
 
 extern "C" int32_t tsf_format_slot(int32_t m, int32_t n, int32_t p) { return format_slot(m, n, p); }
+
+namespace {
+// FNV-1a over the little-endian bytes of one value
+template <typename V>
+void fnv1a(uint64_t &h, V v)
+{
+    uint64_t u = (uint64_t)v;
+    for (size_t b = 0; b < sizeof(V); ++b) {
+        h ^= (u >> (8 * b)) & 0xFF;
+        h *= 0x100000001B3ull;
+    }
+}
+}  // namespace
+
+extern "C" uint64_t tsf_params_hash(const tsf_walk_params *prm)
+{
+    if (!prm) return 0;
+    uint64_t h = 0xCBF29CE484222325ull;
+    fnv1a(h, prm->base_seed);
+    fnv1a(h, prm->first_walk_id);
+    fnv1a(h, prm->max_iters);
+    fnv1a(h, prm->plateau);
+    fnv1a(h, prm->t_eq);
+    fnv1a(h, prm->t_reduce);
+    fnv1a(h, prm->t_expand);
+    fnv1a(h, prm->flip_tries);
+    fnv1a(h, prm->restart_from_best);
+    fnv1a(h, prm->objective);
+    return h ? h : 1;
+}
+
+extern "C" tsf_status tsf_walk_check(const tsf_walk_params *prm, const tsf_walk_header *hdr,
+                                     int32_t n_walks, int32_t *n_mismatched)
+{
+    if (n_mismatched) *n_mismatched = 0;
+    if (!prm || (n_walks > 0 && !hdr) || n_walks < 0)
+        return fail(TSF_E_ARG, "tsf_walk_check: null argument or n_walks < 0");
+    const uint64_t want = tsf_params_hash(prm);
+    int32_t bad = 0;
+    for (int32_t w = 0; w < n_walks; ++w)
+        if ((hdr[w].params_hash != 0 && hdr[w].params_hash != want) || hdr[w].done == -3) ++bad;
+    if (n_mismatched) *n_mismatched = bad;
+    if (bad)
+        return fail(TSF_E_STATE, "%d walks were run with other walk parameters", (int)bad);
+    return TSF_OK;
+}

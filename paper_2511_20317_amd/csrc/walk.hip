@@ -67,6 +67,8 @@ __global__ void __launch_bounds__(64) init_kernel(tsf_walk_header *hdr, uint64_t
         h->t = 0;
         h->plateau_start = 0;
         for (int c = 0; c < 12; ++c) h->counters[c] = 0;
+        h->params_hash = 0;
+        h->reserved = 0;
     }
 }
 
@@ -871,6 +873,7 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
         return tsf_fail(TSF_E_CAPACITY, "%zu bytes of LDS per workgroup exceed 160 KiB", L.lds);
     std::memset(&a, 0, sizeof a);
     a.base_seed = prm->base_seed;
+    a.params_hash = tsf_params_hash(prm);
     a.first_walk_id = prm->first_walk_id;
     a.max_iters = prm->max_iters;
     a.plateau = prm->plateau;

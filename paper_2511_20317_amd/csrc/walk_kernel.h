@@ -52,6 +52,7 @@ namespace tsfk {
 
 struct KArgs {
     uint64_t base_seed;
+    uint64_t params_hash;  // tsf_params_hash of the call's parameters
     int64_t first_walk_id;
     int64_t max_iters;
     int64_t plateau;
@@ -1630,6 +1631,12 @@ __global__ void __launch_bounds__(256) __attribute__((
         if (!sane && wk.gl == 0 && done == 0) h->done = -1;
         return;
     }
+    // a walk resumed with other parameters than it was run with is not
+    // advanced (tsf_walk_check reports it)
+    if (h->params_hash != 0 && h->params_hash != a.params_hash) {
+        if (wk.gl == 0) h->done = -3;
+        return;
+    }
     wk.seed = a.base_seed + (uint64_t)(a.first_walk_id + walk);
     wk.r = h->rank;
     wk.r_cap = h->r_cap;
@@ -1685,6 +1692,7 @@ __global__ void __launch_bounds__(256) __attribute__((
         h->n_rec = wk.n_rec;
         h->t = wk.t;
         h->plateau_start = wk.plateau_start;
+        h->params_hash = a.params_hash;
         // every iteration of this call is a flip or a dead end
         wk.cnt[C_ITERS] = (uint32_t)(wk.t - t_first);
         wk.cnt[C_FLIPS] = wk.cnt[C_ITERS] - wk.cnt[C_DEAD_ENDS];

@@ -190,7 +190,7 @@ def time_to_ranks(ctx, scheme, n_walks, r_cap, ladder, wall_s, base_seed, net=No
     kw.update(prm_kw or {})
     prm = tsf.walk_params(**kw)
     ws = tsf.LearnWorkspace(n_walks) if net is not None else None
-    best_col = b.hdr.view(torch.int32).view(n_walks, 40)[:, 7]
+    best_col = b.hdr.view(torch.int32).view(n_walks, tsf.HEADER_I32)[:, 7]
     iters_per_call = iters_per_call or (20 if net is not None else 2000)
     hit_s = {}
     done_iters = 0

@@ -22,6 +22,7 @@ EQ_ACCEPT = 42949673            # round(0.01 * 2^32): Algorithm 1's 1% equal-ran
 STATUS = {0: "TSF_OK", -1: "TSF_E_ARG", -2: "TSF_E_FORMAT", -3: "TSF_E_CAPACITY",
           -4: "TSF_E_NOT_TERNARY", -5: "TSF_E_INVALID_SCHEME", -6: "TSF_E_DEVICE",
           -7: "TSF_E_STATE"}
+TSF_E_STATE = -7
 
 COUNTER_NAMES = ("iters", "flips", "attempts", "fallbacks", "dead_ends", "zero_removed",
                  "merges", "expands", "expand_fails", "restarts", "eq_accepts",
@@ -98,13 +99,15 @@ class MlpC(C.Structure):
 MLP_IN, MLP_HID, MLP_NPARAM, MLP_NBF16 = 512, 256, 197380, 262400
 
 
-# numpy view of tsf_walk_header (160 bytes)
+# numpy view of tsf_walk_header (176 bytes)
 HEADER_DTYPE = np.dtype([("m", "<i4"), ("n", "<i4"), ("p", "<i4"), ("mode", "<i4"),
                          ("r_cap", "<i4"), ("target_rank", "<i4"), ("rank", "<i4"),
                          ("best_rank", "<i4"), ("start_rank", "<i4"), ("done", "<i4"),
                          ("n_rec", "<i4"), ("best_nnz", "<i4"), ("t", "<i8"),
-                         ("plateau_start", "<i8"), ("counters", "<i8", (12,))])
-assert HEADER_DTYPE.itemsize == 160
+                         ("plateau_start", "<i8"), ("counters", "<i8", (12,)),
+                         ("params_hash", "<u8"), ("reserved", "<u8")])
+assert HEADER_DTYPE.itemsize == 176
+HEADER_I32 = HEADER_DTYPE.itemsize // 4   # int32 columns of a header (views of hdr)
 RECORD_DTYPE = np.dtype([("iter", "<i8"), ("rank", "<i4"), ("reserved", "<i4")])
 
 _lib = None
@@ -154,6 +157,7 @@ def lib():
             ("tsf_walk_learned", [C.c_void_p, P(WalkParams), P(WalkBatchC), P(MlpC), P(LearnWsC),
                                   C.c_int64, P(Launch), C.c_void_p]),
             ("tsf_format_slot", [C.c_int32, C.c_int32, C.c_int32]),
+            ("tsf_walk_check", [P(WalkParams), C.c_void_p, C.c_int32, P(C.c_int32)]),
             ("tsf_scheme_invariants", [P(CScheme), C.c_void_p, P(InvariantsC)]),
             ("tsf_meta_swap", [P(CScheme), P(CScheme)]),
             ("tsf_lift", [P(CScheme), C.c_int64, C.c_int32, P(CScheme), P(LiftResultC)]),
@@ -173,6 +177,8 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = C.c_int
+        L.tsf_params_hash.argtypes = [P(WalkParams)]
+        L.tsf_params_hash.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -376,6 +382,21 @@ def walk_params(base_seed=0, first_walk_id=0, max_iters=100000, plateau=20000, f
                       restart_from_best, t_eq, t_reduce, t_expand, objective, 0)
 
 
+def params_hash(prm: WalkParams) -> int:
+    return int(lib().tsf_params_hash(C.byref(prm)))
+
+
+def walk_check(prm: WalkParams, headers: np.ndarray):
+    """tsf_walk_check on host headers (HEADER_DTYPE); returns the status
+    (0 or TSF_E_STATE) and leaves the count in walk_check.mismatched."""
+    h = np.ascontiguousarray(headers, dtype=HEADER_DTYPE)
+    n = C.c_int32(0)
+    st = lib().tsf_walk_check(C.byref(prm), h.ctypes.data_as(C.c_void_p), int(h.size),
+                              C.byref(n))
+    walk_check.mismatched = int(n.value)
+    return st
+
+
 class Context:
     def __init__(self):
         self.ptr = C.c_void_p()
@@ -484,6 +505,12 @@ class WalkBatch:
         la = Launch(lanes_per_walk, waves_per_block, strategy)
         check(lib().tsf_walk(ctx.ptr, C.byref(prm), C.byref(self.c()), int(n_iters),
                              C.byref(la), self._stream()))
+
+    def check_resume(self, prm: WalkParams):
+        """tsf_walk_check on a host copy of the headers: raises TsfError
+        (TSF_E_STATE) if some walk was run with other walk parameters."""
+        h = np.ascontiguousarray(self.headers())
+        check(walk_check(prm, h))
 
     def autotune(self, ctx: Context, prm: WalkParams, trial_iters=200):
         """Time every launch configuration on a copy of the state; returns the

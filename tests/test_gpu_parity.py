@@ -352,3 +352,35 @@ def test_additions_objective_z2(ctx, ranked_schemes, strategy):
     prm = tsf.walk_params(base_seed=17, max_iters=3000, plateau=1000, objective=tsf.OBJ_ADDITIONS)
     b = _run(ctx, groups, prm, 3000, strategy=strategy, lanes=16)
     compare(b, run_oracle(groups, prm, range(32), 3000), "additions z2 s=%d" % strategy)
+
+
+def test_resume_with_other_parameters_is_refused(ctx):
+    """A batch run with one set of walk parameters and resumed with another:
+    no walk is advanced, each is marked done = -3, and the resume check
+    reports TSF_E_STATE; resuming with the original parameters continues
+    the walks exactly as an uninterrupted run (bit for bit against the
+    oracle)."""
+    groups = [(_std(3, 3, 3), 16, 35, 0)]
+    prm = tsf.walk_params(base_seed=3, max_iters=1500, plateau=600)
+    b = tsf.WalkBatch(groups, rec_cap=16)
+    b.init(ctx)
+    b.walk(ctx, prm, 700)
+    b.check_resume(prm)
+    before = b.headers()
+    other = tsf.walk_params(base_seed=4, max_iters=1500, plateau=600)
+    with pytest.raises(tsf.TsfError):
+        b.check_resume(other)
+    b.walk(ctx, other, 300)
+    after = b.headers()
+    assert (after["done"] == -3).all()
+    assert np.array_equal(after["t"], before["t"])
+    assert np.array_equal(after["counters"], before["counters"])
+    with pytest.raises(tsf.TsfError):
+        b.check_resume(prm)
+    # the same walks resumed with their own parameters continue exactly
+    c = tsf.WalkBatch(groups, rec_cap=16)
+    c.init(ctx)
+    c.walk(ctx, prm, 700)
+    c.walk(ctx, prm, 800)
+    c.check_resume(prm)
+    compare(c, run_oracle(groups, prm, range(16), 1500), "resume")

@@ -326,3 +326,47 @@ def test_error_paths_of_the_host_calls(lib):
     assert b"" != lib.tsf_last_error()
     # the same calls in range succeed
     assert lib.tsf_meta_project(C.byref(s.c()), 2, 1, C.byref(cs)) == 0
+
+
+def _fnv1a_params(prm):
+    """FNV-1a (64-bit) over the little-endian bytes of the resume-relevant
+    walk parameters, written out independently of the library."""
+    import struct
+    h = 0xCBF29CE484222325
+    data = struct.pack("<QqqqQQQiii", prm.base_seed, prm.first_walk_id, prm.max_iters,
+                       prm.plateau, prm.t_eq, prm.t_reduce, prm.t_expand, prm.flip_tries,
+                       prm.restart_from_best, prm.objective)
+    for byte in data:
+        h ^= byte
+        h = (h * 0x100000001B3) % (1 << 64)
+    return h or 1
+
+
+def test_params_hash_and_resume_check(lib):
+    """tsf_walk_check (host, no GPU): walks whose headers carry the hash of
+    other parameters than the resuming call's are reported as TSF_E_STATE;
+    fresh headers (hash 0) and headers of the same parameters pass."""
+    a = tsf.walk_params(base_seed=5, max_iters=1000, plateau=300)
+    variants = [tsf.walk_params(base_seed=6, max_iters=1000, plateau=300),
+                tsf.walk_params(base_seed=5, max_iters=1001, plateau=300),
+                tsf.walk_params(base_seed=5, max_iters=1000, plateau=301),
+                tsf.walk_params(base_seed=5, max_iters=1000, plateau=300, flip_tries=6),
+                tsf.walk_params(base_seed=5, max_iters=1000, plateau=300, restart_from_best=1),
+                tsf.walk_params(base_seed=5, max_iters=1000, plateau=300, t_expand=1),
+                tsf.walk_params(base_seed=5, max_iters=1000, plateau=300, objective=1),
+                tsf.walk_params(base_seed=5, first_walk_id=3, max_iters=1000, plateau=300)]
+    ha = tsf.params_hash(a)
+    assert ha == _fnv1a_params(a)
+    assert len({ha} | {tsf.params_hash(v) for v in variants}) == len(variants) + 1
+    hdr = np.zeros(6, tsf.HEADER_DTYPE)
+    assert tsf.walk_check(a, hdr) == 0 and tsf.walk_check.mismatched == 0
+    hdr["params_hash"] = ha
+    assert tsf.walk_check(a, hdr) == 0
+    for v in variants:
+        assert tsf.walk_check(v, hdr) == tsf.TSF_E_STATE
+        assert tsf.walk_check.mismatched == 6
+    hdr["params_hash"][2] = 0
+    hdr["done"][4] = -3
+    assert tsf.walk_check(a, hdr) == tsf.TSF_E_STATE and tsf.walk_check.mismatched == 1
+    assert tsf.walk_check(variants[0], hdr) == tsf.TSF_E_STATE
+    assert tsf.walk_check.mismatched == 5
