@@ -250,9 +250,11 @@ def run_large(ctx, args):
     fmts = [(4, 5, 12), (5, 6, 10), (6, 7, 9)]
     per = args.walks // 3
     groups = [(tsf.init_scheme(*f), per, f[0] * f[1] * f[2] + 8, 0) for f in fmts]
-    # room for the extend: a projected scheme has at most r0 terms and the
-    # extend along p appends m*n, and the walk there may expand 8 more
-    cap = max(f[0] * f[1] * f[2] + f[0] * f[1] + 8 for f in fmts)
+    # capacities: r0 + 8 in the format and after the project (a projected
+    # scheme has at most r0 terms); room for the extend back (+ m*n naive
+    # terms) in the last phase
+    cap = max(f[0] * f[1] * f[2] + 8 for f in fmts)
+    cap_ext = max(f[0] * f[1] * f[2] + f[0] * f[1] + 8 for f in fmts)
     b = tsf.WalkBatch(groups, capacity=cap, rec_cap=32)
     prm = tsf.walk_params(base_seed=0, max_iters=10 ** 9, plateau=50000)
     b.init(ctx)
@@ -294,7 +296,7 @@ def run_large(ctx, args):
     small.meta_from(b, 1, np.ones(n), np.full(n, 2), idx, r_cap_extra=8)
     small.init(ctx)
     walk_phase(small, "projected")
-    back = tsf.WalkBatch.empty(n, cap, tsf.TSF_TERNARY, max_len=63, rec_cap=32)
+    back = tsf.WalkBatch.empty(n, cap_ext, tsf.TSF_TERNARY, max_len=63, rec_cap=32)
     back.meta_from(small, 1, np.full(n, 2), np.full(n, 2), np.zeros(n), r_cap_extra=8)
     back.init(ctx)
     hb = back.headers()

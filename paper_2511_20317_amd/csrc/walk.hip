@@ -615,8 +615,8 @@ KernelFn pick_kernel(int g, int s, bool wide, bool z2, int strategy)
 
 int slots_for(int cap, int g)
 {
-    for (int s : {1, 2, 4, 8})
-        if (s * g >= cap) return s;
+    for (int s : {1, 2, 4, 5, 6, 7, 8})
+        if (s * g >= cap && (g == 64 || (s & (s - 1)) == 0)) return s;
     return -1;
 }
 

@@ -16,7 +16,8 @@ namespace tsfk {
 using Word = std::conditional_t<TSFK_WIDE != 0, uint64_t, uint32_t>;
 constexpr bool kZ2 = TSFK_Z2 != 0;
 
-// term-parallel kernels: S = term slots per lane
+// term-parallel kernels: S = term slots per lane (with 64 lanes per walk
+// also 5, 6 and 7, so that large schemes are not rounded up to 8 slots)
 template <int G>
 KernelFn pick_s(int s)
 {
@@ -25,8 +26,17 @@ KernelFn pick_s(int s)
     case 2: return walk_kernel<G, 2, Word, kZ2, false, false>;
     case 4: return walk_kernel<G, 4, Word, kZ2, false, false>;
     case 8: return walk_kernel<G, 8, Word, kZ2, false, false>;
-    default: return nullptr;
+    default: break;
     }
+    if constexpr (G == 64) {
+        switch (s) {
+        case 5: return walk_kernel<G, 5, Word, kZ2, false, false>;
+        case 6: return walk_kernel<G, 6, Word, kZ2, false, false>;
+        case 7: return walk_kernel<G, 7, Word, kZ2, false, false>;
+        default: break;
+        }
+    }
+    return nullptr;
 }
 
 // attempt-parallel kernels: indexed (at most 64 terms; pk: factors of at

@@ -138,11 +138,21 @@ def test_z2_mode(ctx, strategy):
     assert (b.verify_device(which=0).cpu().numpy() == 0).all()
 
 
-def test_large_formats_64bit_masks(ctx):
-    groups = [(_std(4, 5, 12), 3, 248, 0), (_std(6, 7, 9), 2, 386, 0)]
-    prm = tsf.walk_params(base_seed=9, max_iters=300, plateau=200, t_expand=1 << 28)
-    b = _run(ctx, groups, prm, 300, lanes=64, wpb=1)
-    compare(b, run_oracle(groups, prm, range(5), 300), "large")
+@pytest.mark.parametrize("capacity,wpb", [(None, 1), (300, 1), (386, 2), (448, 1), (512, 1)])
+def test_large_formats_64bit_masks(ctx, capacity, wpb):
+    """Term-parallel kernels with 64 lanes per walk and 64-bit masks on large
+    formats, with expands, restarts and a round split, at batch capacities
+    that need 4, 5, 7, 7 and 8 term slots per lane."""
+    groups = [(_std(4, 5, 12), 3, 248, 0), (_std(5, 6, 10), 2, 300, 0)]
+    if capacity is None or capacity >= 386:
+        groups.append((_std(6, 7, 9), 2, 386, 0))
+    if capacity is None:
+        groups = groups[:1]
+    prm = tsf.walk_params(base_seed=9, max_iters=600, plateau=200, t_expand=1 << 28)
+    n = sum(g[1] for g in groups)
+    b = _run(ctx, groups, prm, 600, splits=[250, 350], lanes=64, wpb=wpb, capacity=capacity,
+             strategy=2)
+    compare(b, run_oracle(groups, prm, range(n), 600), "large cap=%s" % capacity)
     assert (b.verify_device(which=1).cpu().numpy() == 0).all()
 
 
