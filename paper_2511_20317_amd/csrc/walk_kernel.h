@@ -871,9 +871,8 @@ struct Walker {
             Ai = ld(i, A);
             Bi = ld(i, B);
         }
-        do {
-            const int kk = match.pop();
-            bool v0, v1;
+        // the two roles of the flip with term kk
+        const auto roles = [&](int kk, bool &v0, bool &v1) {
             if constexpr (PK) {
                 roles_packed(wx, wa, wb, lds[idx(kk, X)], lds[idx(kk, A)], lds[idx(kk, B)],
                              v0, v1);
@@ -890,6 +889,27 @@ struct Walker {
                 v0 = a1 && b1 && keep;
                 v1 = a2 && b2 && keep;
             }
+        };
+        if (NW == 1 && !__ballot(r > 32)) {
+            // every walk of the wavefront has at most 32 terms: the sets fit
+            // in 32-bit words
+            uint32_t mm = (uint32_t)match.w[0], s0 = 0, s1 = 0;
+            do {
+                const int kk = __builtin_ctz(mm);
+                mm &= mm - 1;
+                bool v0, v1;
+                roles(kk, v0, v1);
+                s0 |= (v0 ? 1u : 0u) << kk;
+                s1 |= (v1 ? 1u : 0u) << kk;
+            } while (mm);
+            m0.w[0] = s0;
+            m1.w[0] = s1;
+            return;
+        }
+        do {
+            const int kk = match.pop();
+            bool v0, v1;
+            roles(kk, v0, v1);
             m0.set_if(kk, v0);
             m1.set_if(kk, v1);
         } while (match.any());
