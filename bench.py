@@ -457,6 +457,45 @@ def run_learned_walk(ctx, args):
     return out
 
 
+def run_222(ctx, args):
+    """The (2,2,2) workload: 256 walks from the standard rank-8 scheme, seed
+    0, at most 1e5 iterations, plateau 2e4, target rank 7; rounds of
+    args.iters iterations until every walk stopped.  Reports flips/s, the
+    wall time until the first walk reached 7 (end of that round), the share
+    of walks at 7 and the Brent check of every best scheme."""
+    import torch
+    from paper_2511_20317_amd import tsf
+    n = 256
+    b = tsf.WalkBatch([(tsf.init_scheme(2, 2, 2), n, 16, 7)], rec_cap=16)
+    prm = tsf.walk_params(base_seed=0, max_iters=100000, plateau=20000)
+    b.init(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first, done_iters, rounds = None, 0, 0
+    while done_iters < 100000:
+        b.walk(ctx, prm, args.iters)
+        done_iters += args.iters
+        rounds += 1
+        hdr = b.headers()
+        if first is None and (hdr["best_rank"] <= 7).any():
+            first = {"s": time.perf_counter() - t0, "iterations": done_iters}
+        if (hdr["done"] != 0).all():
+            break
+    wall = time.perf_counter() - t0
+    hdr = b.headers()
+    nv = b.verify_device(1).cpu().numpy()
+    rec = b.rec.cpu().numpy()
+    n_rec = np.minimum(hdr["n_rec"], b.rec_cap)
+    first_it = [int(rec[w, :n_rec[w], 0][(rec[w, :n_rec[w], 1] & 0xFFFFFFFF) <= 7].min())
+                for w in range(n) if hdr["best_rank"][w] <= 7]
+    return {"flips_per_s": int(hdr["counters"][:, 1].sum()) / wall, "wall_s": wall,
+            "round_iters": args.iters, "rounds": rounds, "first_rank_7": first,
+            "walks_at_7": int((hdr["best_rank"] <= 7).sum()),
+            "median_iterations_to_7": float(np.median(first_it)) if first_it else None,
+            "max_iterations_to_7": int(max(first_it)) if first_it else None,
+            "best_schemes_failing_brent": int((nv != 0).sum())}
+
+
 def time_to_rank_fine(ctx, args, target=23, round_iters=1000, limit_s=60.0):
     """Time to the target rank with rounds of round_iters iterations: a fresh
     batch of the (3,3,3) workload is walked round by round (the best rank is
@@ -512,7 +551,7 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter scale)")
     ap.add_argument("--workload", default="333",
-                    choices=["333", "mixed", "large", "additions", "explore", "lift",
+                    choices=["333", "222", "mixed", "large", "additions", "explore", "lift",
                              "learned-walk"],
                     help="333: the (3,3,3) benchmark; mixed / large / additions: the other "
                          "workloads")
@@ -543,12 +582,15 @@ def main():
     if args.workload != "333":
         args.iters = args.iters or 100000
         res = {"mixed": run_mixed, "large": run_large, "additions": run_additions,
-               "explore": run_explore, "lift": run_lift,
+               "explore": run_explore, "lift": run_lift, "222": run_222,
                "learned-walk": run_learned_walk}[args.workload](ctx, args)
         if args.workload == "mixed":
             value = res["ternary"]["flips_per_s"]
             desc = ("131,072 walks over (3,3,4), (3,4,5), (4,4,4), (4,4,5) in one launch, "
                     "ternary then Z2")
+        elif args.workload == "222":
+            value = res["flips_per_s"]
+            desc = "256 (2,2,2) walks from the standard rank-8 scheme to rank 7"
         elif args.workload == "explore":
             value = res["flips_per_s"]
             desc = ("exploratory search: 4 x %d walks from (2,2,2), (2,2,3), (2,3,3), (3,3,3), "
@@ -569,14 +611,16 @@ def main():
             desc = ("98,304 walks over (4,5,12), (5,6,10), (6,7,9) with device project to "
                     "p-1 and extend back between rounds")
         out = {"metric": "flips/sec on 1 GPU", "value": value, "unit": "flips/s", "n_gpus": 1,
-               "steps": args.steps, "warmup": 0, "higher_is_better": True, "scaling": "weak",
+               "steps": res["rounds"] if args.workload == "222" else args.steps,
+               "warmup": 0, "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None,
                "dtype": ("u64" if args.workload in ("large", "explore") else
                          "u32/bf16" if args.workload == "learned-walk" else "u32"),
                "data": "synthetic",
                "config": ({"workload": desc, "walks": args.ab_walks, "seconds": args.ab_seconds}
                           if args.workload == "learned-walk" else
-                          {"workload": desc, "walks": args.walks, "iters_per_step": args.iters}),
+                          {"workload": desc, "walks": 256 if args.workload == "222" else args.walks,
+                           "iters_per_step": args.iters}),
                "results": res}
         print(json.dumps(out))
         return
