@@ -91,6 +91,12 @@ def cpu_baseline(n_walks=512, iters=100000, threads=None):
                          flips / dt / threads)}
 
 
+def _median_or_none(xs):
+    """Median of xs, None when it is infinite (most runs did not get there)."""
+    m = float(np.median(xs))
+    return m if np.isfinite(m) else None
+
+
 def learned_vs_uniform(ctx, args):
     """The learned proposal: a network (512 -> 256 -> 256 -> 1, bf16 on the
     matrix cores) scores the candidates of an iteration's attempts and the
@@ -103,7 +109,7 @@ def learned_vs_uniform(ctx, args):
     candidates, and uniform proposals, over seed blocks); and learned against
     uniform proposals at equal wall time on (3,3,3) (and (4,4,4) with
     --learned-444): medians over R disjoint seed blocks of the time to each
-    rank of the ladder (inf where a run does not reach it)."""
+    rank of the ladder (null where the median run does not reach it)."""
     import torch
     from paper_2511_20317_amd import learn, tsf
     s222, s333 = tsf.init_scheme(2, 2, 2), tsf.init_scheme(3, 3, 3)
@@ -178,10 +184,10 @@ def learned_vs_uniform(ctx, args):
         summ = {}
         for mode, rs in runs.items():
             summ[mode] = {
-                "median_time_to_rank_s": {str(k): float(np.median([r["time_to_rank_s"].get(k, np.inf)
-                                                                  for r in rs])) for k in ladder},
-                "median_iters_to_rank": {str(k): float(np.median([r["iters_to_rank"].get(k, np.inf)
-                                                                 for r in rs])) for k in ladder},
+                "median_time_to_rank_s": {str(k): _median_or_none([r["time_to_rank_s"].get(k, np.inf)
+                                                                   for r in rs]) for k in ladder},
+                "median_iters_to_rank": {str(k): _median_or_none([r["iters_to_rank"].get(k, np.inf)
+                                                                  for r in rs]) for k in ladder},
                 "iterations_per_s": float(np.median([r["iterations"] / r["wall_s"] for r in rs])),
                 "best_rank_median": float(np.median([r["best_rank"] for r in rs])),
             }
