@@ -739,13 +739,49 @@ struct Walker {
     }
 
     // ------------------------------------------------------------------ TP
+    // With four or more slots per lane the three factors of this lane's S
+    // terms (k = q*G + lane, indexes clamped to the rows) are read in one
+    // round: the attempts and the cyclic search of an iteration compare
+    // against these registers, since no term changes before a flip is
+    // chosen.  With fewer slots each attempt reads the factors it compares
+    // (measured faster there).
+    static constexpr bool kRegSlots = !AP && S >= 4;
+    __device__ __forceinline__ void load_slots(TV<T> (&F)[S][3]) const
+    {
+        if constexpr (!kRegSlots) return;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int k = q * G + gl;
+            load_term(k < cap2 ? k : cap2 - 1, F[q]);
+        }
+    }
+
     // Candidate partners of (i, X): lane-parallel over the terms, one ballot
     // per slot and role.  m0/m1: role 0/1 masks (bit = lane of slot q).
-    // Factor X of every slot is read first, at an index clamped to the walk's
-    // rows, so that the reads issue back to back; the validity of the two
+    // Factor X of every slot is compared first (read back to back at indexes
+    // clamped to the walk's rows, or taken from F); the validity of the two
     // roles is evaluated only when some lane of the group has a match.
-    __device__ void candidates_tp(int i, int X, uint64_t (&m0)[S], uint64_t (&m1)[S], int &n0,
-                                  int &n1) const
+    __device__ void candidates_tp(int i, int X, const TV<T> (&F)[S][3], uint64_t (&m0)[S],
+                                  uint64_t (&m1)[S], int &n0, int &n1) const
+    {
+        if constexpr (kRegSlots) {
+            // X is wave-uniform: one specialisation per kind, so the slot
+            // factors are picked from F at compile time
+            if (X == 0)
+                candidates_tp_x<0>(i, F, m0, m1, n0, n1);
+            else if (X == 1)
+                candidates_tp_x<1>(i, F, m0, m1, n0, n1);
+            else
+                candidates_tp_x<2>(i, F, m0, m1, n0, n1);
+        } else {
+            candidates_tp_lds(i, X, m0, m1, n0, n1);
+        }
+    }
+
+    // the same from LDS, one code path for the three kinds (the smaller code
+    // measured faster with few slots)
+    __device__ void candidates_tp_lds(int i, int X, uint64_t (&m0)[S], uint64_t (&m1)[S],
+                                      int &n0, int &n1) const
     {
         const int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
         const TV<T> xi = ld(i, X);
@@ -769,6 +805,45 @@ struct Walker {
             if (sg[q] != 0) {
                 const int k = q * G + gl;
                 const TV<T> Ak = ld(k, A), Bk = ld(k, B);
+                TV<T> o1, o2;
+                const bool a1 = axpy(sg[q], Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
+                const bool a2 = axpy(sg[q], Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
+                const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
+                v0 = a1 && b1 && keep;
+                v1 = a2 && b2 && keep;
+            }
+            m0[q] = gballot(v0);
+            m1[q] = gballot(v1);
+            n0 += popc64(m0[q]);
+            n1 += popc64(m1[q]);
+        }
+    }
+
+    template <int X>
+    __device__ void candidates_tp_x(int i, const TV<T> (&F)[S][3], uint64_t (&m0)[S],
+                                    uint64_t (&m1)[S], int &n0, int &n1) const
+    {
+        constexpr int A = X == 0 ? 1 : 0, B = X == 2 ? 1 : 2;
+        // term i's factors (one broadcast round of reads; taking them from
+        // the registers of the lane that holds term i measured slower)
+        const TV<T> xi = ld(i, X), Ai = ld(i, A), Bi = ld(i, B);
+        int sg[S];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int k = q * G + gl;
+            sg[q] = (k < r && k != i) ? rel(xi, F[q][X], X) : 0;
+            any |= sg[q] != 0;
+        }
+        n0 = n1 = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) m0[q] = m1[q] = 0;
+        if (!gballot(any)) return;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            bool v0 = false, v1 = false;
+            if (sg[q] != 0) {
+                const TV<T> Ak = F[q][A], Bk = F[q][B];
                 TV<T> o1, o2;
                 const bool a1 = axpy(sg[q], Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
                 const bool a2 = axpy(sg[q], Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
@@ -1012,6 +1087,8 @@ struct Walker {
             cnt[C_ATTEMPTS] += (uint32_t)T_;
             return fallback_ap();
         } else {
+            TV<T> F[S][3];
+            load_slots(F);
             uint64_t m0[S], m1[S];
             int n0, n1;
             for (int att = 0; att < T_; ++att) {
@@ -1020,7 +1097,7 @@ struct Walker {
                 cnt[C_ATTEMPTS]++;
                 const int i = (int)below(w0, (uint32_t)r);
                 const int X = (int)below(w1, 3u);
-                candidates_tp(i, X, m0, m1, n0, n1);
+                candidates_tp(i, X, F, m0, m1, n0, n1);
                 const int n = n0 + n1;
                 if (n > 0) {
                     int c = (int)below(w2, (uint32_t)n);
@@ -1030,7 +1107,7 @@ struct Walker {
                     return pack_flip(i, j, X, role);
                 }
             }
-            return fallback_tp();
+            return fallback_tp(F);
         }
     }
 
@@ -1039,7 +1116,7 @@ struct Walker {
     // pair p0 = U(w3 of (t,0,0), 3r); the pairs p = 3i + X are visited
     // cyclically from p0 and the first pair with a valid partner yields
     // candidate U(w3 of (t,1,0), n).  None at all: a dead end.
-    __device__ uint32_t fallback_tp()
+    __device__ uint32_t fallback_tp(const TV<T> (&F)[S][3])
     {
         cnt[C_FALLBACKS]++;
         uint64_t m0[S], m1[S];
@@ -1051,7 +1128,7 @@ struct Walker {
             int p = p0 + q;
             if (p >= npairs) p -= npairs;
             const int i = p / 3, X = p - 3 * i;
-            candidates_tp(i, X, m0, m1, n0, n1);
+            candidates_tp(i, X, F, m0, m1, n0, n1);
             const int n = n0 + n1;
             if (n == 0) continue;
             int c = (int)below(f1, (uint32_t)n);
@@ -1138,8 +1215,9 @@ struct Walker {
             return;
         }
         // U slots per round, their terms read before any is compared (indexes
-        // clamped to the walk's rows), so the reads of a round overlap
-        constexpr int U = 2;
+        // clamped to the walk's rows), so the reads of a round overlap; the
+        // term-parallel kernels with four or more slots read all at once
+        constexpr int U = kRegSlots ? S : 2;
         const int qend = (wave_max_r() + G - 1) / G;
 #pragma unroll 1
         for (int q0 = 0; q0 < qend; q0 += U) {
