@@ -243,7 +243,9 @@ typedef struct {
     int32_t done;              /* 1 once the target was reached; -1 header does
                                   not fit the batch; -2 invalid start scheme;
                                   -3 resumed with other walk parameters than the
-                                  walk was run with (TSF_E_STATE)               */
+                                  walk was run with (TSF_E_STATE); -4 an
+                                  invariant check of tsf_walk_checked failed
+                                  (error word in `reserved`)                     */
     int32_t n_rec;             /* strict improvements so far (records kept up to
                                   the batch's rec_cap)                            */
     int32_t best_nnz;          /* non-zero coefficients of the best scheme        */
@@ -254,7 +256,9 @@ typedef struct {
                                   restarts, eq_accepts, improvements              */
     uint64_t params_hash;      /* tsf_params_hash of the parameters of the walk's
                                   last tsf_walk call; 0 after tsf_walk_init       */
-    uint64_t reserved;
+    uint64_t reserved;         /* done = -4: (iteration << 8) | TSF_CHECK_* bits
+                                  of the failed checks (iteration = t when the
+                                  loaded state failed them); else unused          */
 } tsf_walk_header;
 
 /* One strict improvement of a walk's best rank (TSF_OBJ_ADDITIONS: of its
@@ -378,6 +382,36 @@ tsf_status tsf_walk_init(tsf_ctx *ctx, const tsf_walk_batch *b, void *hip_stream
  * TSF_E_DEVICE. */
 tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
                     int64_t n_iters, const tsf_launch *launch, void *hip_stream);
+
+/* tsf_walk with the walk's invariants checked on the GPU after the scheme is
+ * loaded and after every iteration -- a debugging aid for callers that want
+ * a corrupted state (a damaged checkpoint, a kernel fault) to stop a walk at
+ * once instead of producing schemes that only a later Brent check rejects.
+ * The checks, on the terms below the rank: TSF_CHECK_RANK 1 <= rank <=
+ * r_cap and best_rank <= start_rank; TSF_CHECK_ZERO_FACTOR no factor is
+ * zero; TSF_CHECK_CODING signs only where digits are set (none in Z2) and no
+ * entry beyond the factor's length; TSF_CHECK_NORMALISED the first non-zero
+ * entry of u and of v is +1 (Sec. 3.6, ternary only); TSF_CHECK_INDEX (the
+ * indexed strategy) every match mask equals the relation it indexes;
+ * TSF_CHECK_DEAD_SLOTS (packed factors) the slots above the rank hold the
+ * dead-slot word.  A walk that fails a check is not advanced further: its
+ * header gets done = -4 and reserved = (t << 8) | the failed bits, and its
+ * state is written back as it was at that point (not at all when the
+ * loaded state failed).  Walks that pass every check end bit-identical to
+ * tsf_walk with the same arguments.  Kernels exist for the library's
+ * default launch shapes (strategy 0, 8 lanes per walk for the
+ * attempt-parallel strategies, 64 for the term-parallel one, one
+ * wavefront per workgroup); `launch` may be NULL or name one of them, else
+ * TSF_E_ARG.  Slower than tsf_walk (the index check is quadratic in the
+ * rank).  Errors as tsf_walk. */
+#define TSF_CHECK_RANK 1u
+#define TSF_CHECK_ZERO_FACTOR 2u
+#define TSF_CHECK_CODING 4u
+#define TSF_CHECK_NORMALISED 8u
+#define TSF_CHECK_INDEX 16u
+#define TSF_CHECK_DEAD_SLOTS 32u
+tsf_status tsf_walk_checked(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                            int64_t n_iters, const tsf_launch *launch, void *hip_stream);
 
 /* FNV-1a hash (64-bit) of the walk parameters that a resumed walk must keep:
  * base_seed, first_walk_id, max_iters, plateau, t_eq, t_reduce, t_expand,

@@ -10,10 +10,10 @@
 #include <vector>
 
 namespace tsfk {
-KernelFn pick_kernel_w0_z0(int g, int s, int strategy);
-KernelFn pick_kernel_w0_z1(int g, int s, int strategy);
-KernelFn pick_kernel_w1_z0(int g, int s, int strategy);
-KernelFn pick_kernel_w1_z1(int g, int s, int strategy);
+KernelFn pick_kernel_w0_z0(int g, int s, int strategy, bool chk);
+KernelFn pick_kernel_w0_z1(int g, int s, int strategy, bool chk);
+KernelFn pick_kernel_w1_z0(int g, int s, int strategy, bool chk);
+KernelFn pick_kernel_w1_z1(int g, int s, int strategy, bool chk);
 }  // namespace tsfk
 
 namespace {
@@ -607,10 +607,10 @@ __global__ void __launch_bounds__(64) resize_kernel(tsf_walk_batch in, int32_t w
 // ---------------------------------------------------------------------------
 // host side: kernel table and launch
 // ---------------------------------------------------------------------------
-KernelFn pick_kernel(int g, int s, bool wide, bool z2, int strategy)
+KernelFn pick_kernel(int g, int s, bool wide, bool z2, int strategy, bool chk)
 {
-    if (wide) return z2 ? pick_kernel_w1_z1(g, s, strategy) : pick_kernel_w1_z0(g, s, strategy);
-    return z2 ? pick_kernel_w0_z1(g, s, strategy) : pick_kernel_w0_z0(g, s, strategy);
+    if (wide) return z2 ? pick_kernel_w1_z1(g, s, strategy, chk) : pick_kernel_w1_z0(g, s, strategy, chk);
+    return z2 ? pick_kernel_w0_z1(g, s, strategy, chk) : pick_kernel_w0_z0(g, s, strategy, chk);
 }
 
 int slots_for(int cap, int g)
@@ -811,7 +811,7 @@ struct Launch {
 
 // validate a walk call and build its kernel arguments and launch shape
 tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int64_t n_iters,
-                        const tsf_launch *launch, KArgs &a, Launch &L)
+                        const tsf_launch *launch, KArgs &a, Launch &L, bool checked = false)
 {
     tsf_status st = check_batch(b);
     if (st) return st;
@@ -857,7 +857,10 @@ tsf_status prepare_walk(const tsf_walk_params *prm, const tsf_walk_batch *b, int
     // factors of at most 16 entries: the indexed kernels keep each factor's
     // digits and signs in one 32-bit LDS word
     const bool pk = ix && !wide && b->max_len <= 16;
-    L.fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, pk ? 4 : strategy);
+    if (checked && g != (ap ? 8 : 64))
+        return tsf_fail(TSF_E_ARG, "checked walks use %d lanes per walk with this strategy",
+                        ap ? 8 : 64);
+    L.fn = pick_kernel(g, s, wide, b->mode == TSF_Z2, pk ? 4 : strategy, checked);
     if (!L.fn) return tsf_fail(TSF_E_ARG, "no kernel for this configuration");
     const size_t word = wide ? 8 : 4;
     const size_t factor_bytes = pk ? 4 : 2 * word;
@@ -934,6 +937,18 @@ tsf_status tsf_walk(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_bat
     KArgs a;
     Launch L;
     tsf_status st = prepare_walk(prm, b, n_iters, launch, a, L);
+    if (st) return st;
+    if (b->n_walks == 0 || n_iters == 0) return TSF_OK;
+    return run(L, a, (hipStream_t)hip_stream);
+}
+
+tsf_status tsf_walk_checked(tsf_ctx *ctx, const tsf_walk_params *prm, const tsf_walk_batch *b,
+                            int64_t n_iters, const tsf_launch *launch, void *hip_stream)
+{
+    (void)ctx;  // the autotuner's choices are not used: they may name other shapes
+    KArgs a;
+    Launch L;
+    tsf_status st = prepare_walk(prm, b, n_iters, launch, a, L, true);
     if (st) return st;
     if (b->n_walks == 0 || n_iters == 0) return TSF_OK;
     return run(L, a, (hipStream_t)hip_stream);

@@ -234,7 +234,7 @@ struct TermSet {
     }
 };
 
-template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK>
+template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK, bool CHK = false>
 struct Walker {
     static_assert(!IX || AP, "the match index extends the attempt-parallel strategy");
     // PK: a factor of at most 16 entries is one 32-bit LDS word, digits in
@@ -1588,6 +1588,50 @@ struct Walker {
         }
     }
 
+    // CHK: the invariants of the walk state that every step keeps, over the
+    // terms of the group (lanes in parallel): the rank within [1, r_cap] and
+    // the best rank at most the start rank (TSF_CHECK_RANK); every live
+    // factor non-zero (TSF_CHECK_ZERO_FACTOR), signs only where digits are
+    // (and none in Z2) and no entry beyond the factor's length
+    // (TSF_CHECK_CODING); u and v of every live term normalised, Sec. 3.6
+    // (TSF_CHECK_NORMALISED); IX: every mask equal to the relation it
+    // indexes (TSF_CHECK_INDEX); PK: slots at or above the rank dead
+    // (TSF_CHECK_DEAD_SLOTS).  Returns the OR of the failed checks.
+    __device__ uint32_t check_state(const int (&len)[3]) const
+    {
+        uint32_t bad = 0;
+        if (r < 1 || r > r_cap || best_rank > start_rank) bad |= TSF_CHECK_RANK;
+        // terms below the rank, never beyond the capacity (the mask rows)
+        const int rr = r < 0 ? 0 : (r > a->cap ? a->cap : r);
+        for (int k = gl; k < rr; k += G) {
+#pragma unroll
+            for (int X = 0; X < 3; ++X) {
+                const TV<T> v = ld(k, X);
+                if (v.d == 0) bad |= TSF_CHECK_ZERO_FACTOR;
+                if ((v.s & ~v.d) != 0 || (Z2 && v.s != 0)) bad |= TSF_CHECK_CODING;
+                if (len[X] < (int)(8 * sizeof(T)) && (v.d >> len[X]) != 0) bad |= TSF_CHECK_CODING;
+                if (!Z2 && X < 2 && (v.s & v.d & (~v.d + 1)) != 0) bad |= TSF_CHECK_NORMALISED;
+                if constexpr (IX) {
+                    uint64_t want = 0;
+                    for (int j = 0; j < rr; ++j)
+                        want |= (j != k && equiv(ld(j, X), v, X)) ? 1ull << j : 0ull;
+                    if (mk[X * capm + k] != want) bad |= TSF_CHECK_INDEX;
+                }
+            }
+        }
+        if constexpr (PK) {
+            for (int k = rr + gl; k < cap2; k += G)
+#pragma unroll
+                for (int X = 0; X < 3; ++X)
+                    if (lds[idx(k, X)] != kDead) bad |= TSF_CHECK_DEAD_SLOTS;
+        }
+        uint32_t all = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            all |= gballot((bad >> b) & 1u) ? 1u << b : 0u;
+        return all;
+    }
+
     __device__ void iteration()
     {
         begin_iteration();
@@ -1681,14 +1725,12 @@ __device__ __forceinline__ int flen(int m, int n, int p, int X)
     return X == 0 ? m * n : X == 1 ? n * p : p * m;
 }
 
-// Register budgets: the packed indexed kernels (8 or more lanes per walk)
-// are held to 128 VGPRs, four wavefronts per SIMD, which their LDS also
-// allows at (3,3,3) (10,176 bytes per 8-walk wavefront, sixteen per CU); the
-// other indexed kernels with 32-bit masks to 168 VGPRs (three per SIMD, as
-// many as their LDS allows); the rest are not constrained.
-template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK = false>
-__global__ void __launch_bounds__(256) __attribute__((
-    amdgpu_waves_per_eu(PK && G >= 8 ? 4 : (IX && G >= 8 && sizeof(T) == 4) ? 3 : 1))) walk_kernel(KArgs a)
+// The walk kernel's body; CHK adds the invariant checks of
+// tsf_walk_checked (after the scheme is loaded and after every iteration; a
+// walk that fails one stops with done = -4 and the error word
+// (iteration << 8) | failed checks in the header's `reserved`).
+template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK, bool CHK>
+__device__ __forceinline__ void walk_body(const KArgs &a)
 {
     extern __shared__ uint64_t smem_u64[];
     T *smem = reinterpret_cast<T *>(smem_u64);
@@ -1699,7 +1741,7 @@ __global__ void __launch_bounds__(256) __attribute__((
     const int64_t walk = ((int64_t)blockIdx.x * wpb + wave) * W + grp;
     if (walk >= a.n_walks) return;  // the whole group leaves together
 
-    using Wk = Walker<G, S, T, Z2, AP, IX, PK>;
+    using Wk = Walker<G, S, T, Z2, AP, IX, PK, CHK>;
     Wk wk;
     wk.gl = lane % G;
     wk.gshift = grp * G;
@@ -1755,6 +1797,19 @@ __global__ void __launch_bounds__(256) __attribute__((
     wk.fmt_slot = format_slot(m, n, p);
     wk.load_scheme(a.cur + (size_t)walk * a.cap * 6, wk.r);
     if (wk.additions) wk.nnz = wk.count_nnz();
+    uint64_t err = 0;
+    const int len[3] = {flen(m, n, p, 0), flen(m, n, p, 1), flen(m, n, p, 2)};
+    if constexpr (CHK) {
+        const uint32_t bad = wk.check_state(len);
+        if (bad) {
+            // the loaded state is left as it is
+            if (wk.gl == 0) {
+                h->done = -4;
+                h->reserved = ((uint64_t)wk.t << 8) | bad;
+            }
+            return;
+        }
+    }
 
     if constexpr (AP && !IX) {
         if (a.phase == 1) {
@@ -1777,9 +1832,17 @@ __global__ void __launch_bounds__(256) __attribute__((
             if (done || wk.t >= a.max_iters) break;
             wk.t += 1;
             wk.iteration();
+            if constexpr (CHK) {
+                const uint32_t bad = wk.check_state(len);
+                if (bad) {
+                    done = -4;
+                    err = ((uint64_t)wk.t << 8) | bad;
+                    break;
+                }
+            }
         }
     }
-    if (wk.reached()) done = 1;
+    if ((!CHK || done != -4) && wk.reached()) done = 1;
 
     wk.store_scheme(a.cur + (size_t)walk * a.cap * 6);
     if (wk.gl == 0) {
@@ -1791,11 +1854,31 @@ __global__ void __launch_bounds__(256) __attribute__((
         h->t = wk.t;
         h->plateau_start = wk.plateau_start;
         h->params_hash = a.params_hash;
+        if (CHK && done == -4) h->reserved = err;
         // every iteration of this call is a flip or a dead end
         wk.cnt[C_ITERS] = (uint32_t)(wk.t - t_first);
         wk.cnt[C_FLIPS] = wk.cnt[C_ITERS] - wk.cnt[C_DEAD_ENDS];
         for (int c = 0; c < C_NUM; ++c) h->counters[c] += wk.cnt[c];
     }
+}
+
+// Register budgets: the packed indexed kernels (8 or more lanes per walk)
+// are held to 128 VGPRs, four wavefronts per SIMD, which their LDS also
+// allows at (3,3,3) (10,176 bytes per 8-walk wavefront, sixteen per CU); the
+// other indexed kernels with 32-bit masks to 168 VGPRs (three per SIMD, as
+// many as their LDS allows); the rest are not constrained.
+template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK = false>
+__global__ void __launch_bounds__(256) __attribute__((
+    amdgpu_waves_per_eu(PK && G >= 8 ? 4 : (IX && G >= 8 && sizeof(T) == 4) ? 3 : 1))) walk_kernel(KArgs a)
+{
+    walk_body<G, S, T, Z2, AP, IX, PK, false>(a);
+}
+
+// the same walk with the invariant checks (tsf_walk_checked)
+template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK = false>
+__global__ void __launch_bounds__(256) walk_kernel_checked(KArgs a)
+{
+    walk_body<G, S, T, Z2, AP, IX, PK, true>(a);
 }
 
 using KernelFn = void (*)(KArgs);

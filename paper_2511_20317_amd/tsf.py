@@ -23,6 +23,15 @@ STATUS = {0: "TSF_OK", -1: "TSF_E_ARG", -2: "TSF_E_FORMAT", -3: "TSF_E_CAPACITY"
           -4: "TSF_E_NOT_TERNARY", -5: "TSF_E_INVALID_SCHEME", -6: "TSF_E_DEVICE",
           -7: "TSF_E_STATE"}
 TSF_E_STATE = -7
+# invariant checks of tsf_walk_checked (bits of the error word in a header's
+# `reserved` when done = -4)
+CHECK_RANK = 1
+CHECK_ZERO_FACTOR = 2
+CHECK_CODING = 4
+CHECK_NORMALISED = 8
+CHECK_INDEX = 16
+CHECK_DEAD_SLOTS = 32
+DONE_CHECK_FAILED = -4
 
 COUNTER_NAMES = ("iters", "flips", "attempts", "fallbacks", "dead_ends", "zero_removed",
                  "merges", "expands", "expand_fails", "restarts", "eq_accepts",
@@ -144,6 +153,8 @@ def lib():
                               C.c_void_p]),
             ("tsf_walk", [C.c_void_p, P(WalkParams), P(WalkBatchC), C.c_int64, P(Launch),
                           C.c_void_p]),
+            ("tsf_walk_checked", [C.c_void_p, P(WalkParams), P(WalkBatchC), C.c_int64,
+                                  P(Launch), C.c_void_p]),
             ("tsf_verify_batch", [P(WalkBatchC), C.c_int32, C.c_void_p, C.c_void_p]),
             ("tsf_mlp_sync", [P(MlpC), C.c_void_p]),
             ("tsf_mlp_fwd", [P(MlpC), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -501,10 +512,13 @@ class WalkBatch:
         check(lib().tsf_walk_init(ctx.ptr, C.byref(self.c()), self._stream()))
 
     def walk(self, ctx: Context, prm: WalkParams, n_iters: int, lanes_per_walk=0,
-             waves_per_block=0, strategy=0):
+             waves_per_block=0, strategy=0, checked=False):
+        """tsf_walk, or tsf_walk_checked with checked=True (invariants checked
+        after every iteration; a failing walk stops with done = -4)."""
         la = Launch(lanes_per_walk, waves_per_block, strategy)
-        check(lib().tsf_walk(ctx.ptr, C.byref(prm), C.byref(self.c()), int(n_iters),
-                             C.byref(la), self._stream()))
+        fn = lib().tsf_walk_checked if checked else lib().tsf_walk
+        check(fn(ctx.ptr, C.byref(prm), C.byref(self.c()), int(n_iters), C.byref(la),
+                 self._stream()))
 
     def check_resume(self, prm: WalkParams):
         """tsf_walk_check on a host copy of the headers: raises TsfError
