@@ -575,8 +575,8 @@ def main():
     ap.add_argument("--ab-seconds", type=float, default=1.5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the walks shard by walk id with no "
-              "communication, so several GPUs are not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the walks would shard by walk id "
+              "with no communication, and no multi-GPU path is implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
