@@ -107,8 +107,8 @@ def learned_vs_uniform(ctx, args):
     share of walks that reach each rank within a fixed number of iterations,
     for the trained network, an untrained network choosing among the same
     candidates, and uniform proposals, over seed blocks); and learned against
-    uniform proposals at equal wall time on (3,3,3) (and (4,4,4) with
-    --learned-444): medians over R disjoint seed blocks of the time to each
+    uniform proposals at equal wall time on (3,3,3) and (4,4,4) (the latter
+    skipped with --no-learned-444): medians over R disjoint seed blocks of the time to each
     rank of the ladder (null where the median run does not reach it)."""
     import torch
     from paper_2511_20317_amd import learn, tsf
@@ -170,7 +170,7 @@ def learned_vs_uniform(ctx, args):
     # equal wall time
     results = {}
     cases = [((3, 3, 3), 35, (26, 25, 24, 23))]
-    if args.learned_444:
+    if not args.no_learned_444:
         cases.append(((4, 4, 4), 64, (63, 62, 61, 60)))
     for fmt, r_cap, ladder in cases:
         s = tsf.init_scheme(*fmt)
@@ -564,8 +564,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training the proposal network and its comparison with uniform "
                          "proposals")
-    ap.add_argument("--learned-444", action="store_true",
-                    help="also compare learned and uniform proposals at equal wall time on (4,4,4)")
+    ap.add_argument("--no-learned-444", action="store_true",
+                    help="skip the equal-wall-time comparison on (4,4,4)")
     ap.add_argument("--learn-walks", type=int, default=2048,
                     help="(3,3,3) walks logged for training (twice as many (2,2,2) walks)")
     ap.add_argument("--learn-iters", type=int, default=6000)
