@@ -429,6 +429,25 @@ uint64_t tsf_params_hash(const tsf_walk_params *prm);
 tsf_status tsf_walk_check(const tsf_walk_params *prm, const tsf_walk_header *hdr,
                           int32_t n_walks, int32_t *n_mismatched);
 
+/* Host check of a batch's walk state before it is resumed, e.g. one read back
+ * from a checkpoint, so that a damaged state is refused instead of walked.
+ * hdr, cur, best, start: host copies of the batch's
+ * n_walks headers and its three scheme buffers (capacity x 6 uint64 per walk,
+ * the layout of tsf_walk_batch).  Walks flagged by a walk call (done < 0) are
+ * skipped.  For every other walk, in order, the first failing check is
+ * returned and its index written to *first_bad (may be NULL; -1 when all
+ * pass): the format (TSF_E_FORMAT: dims >= 1, factors of at most 64
+ * entries; TSF_E_ARG: mode neither ternary nor Z2); the ranks (TSF_E_CAPACITY:
+ * 0 <= rank <= r_cap <= capacity, best and start ranks within the capacity);
+ * the coding of the current, best and start schemes (TSF_E_NOT_TERNARY: signs
+ * only under digits, none in Z2, no entry beyond a factor's length); with
+ * check_brent != 0 their Brent equations (Eq. 1, TSF_E_INVALID_SCHEME) --
+ * cheap for small formats; tsf_verify_batch does the same on the GPU.
+ * Reads only caller-owned host memory; synchronous. */
+tsf_status tsf_state_check(const tsf_walk_header *hdr, const uint64_t *cur, const uint64_t *best,
+                           const uint64_t *start, int32_t n_walks, int32_t capacity,
+                           int32_t check_brent, int32_t *first_bad);
+
 /* Exact Brent verification (Eq. 1, C^T form of Sec. 3.1) on the GPU of one
  * scheme per walk of the batch: which = 0 checks cur (rank hdr[w].rank),
  * 1 checks best (hdr[w].best_rank), 2 checks start (hdr[w].start_rank).

@@ -567,6 +567,51 @@ extern "C" uint64_t tsf_params_hash(const tsf_walk_params *prm)
     return h ? h : 1;
 }
 
+extern "C" tsf_status tsf_state_check(const tsf_walk_header *hdr, const uint64_t *cur,
+                                      const uint64_t *best, const uint64_t *start, int32_t n_walks,
+                                      int32_t capacity, int32_t check_brent, int32_t *first_bad)
+{
+    if (first_bad) *first_bad = -1;
+    if (n_walks < 0 || capacity < 1 || (n_walks > 0 && (!hdr || !cur || !best || !start)))
+        return fail(TSF_E_ARG, "tsf_state_check: null buffer, n_walks < 0 or capacity < 1");
+    std::vector<int8_t> U((size_t)capacity * 64), V((size_t)capacity * 64), W((size_t)capacity * 64);
+    for (int32_t w = 0; w < n_walks; ++w) {
+        const tsf_walk_header &h = hdr[w];
+        if (h.done < 0) continue;  // flagged by a walk call; never advanced again
+        auto bad = [&](tsf_status st) {
+            if (first_bad) *first_bad = w;
+            return st;
+        };
+        tsf_dims d{h.m, h.n, h.p, 0, capacity, h.mode};
+        tsf_status st = check_dims(d, false);
+        if (st) return bad(st);
+        if (h.r_cap < 0 || h.r_cap > capacity || h.rank < 0 || h.rank > h.r_cap ||
+            h.best_rank < 0 || h.best_rank > capacity || h.start_rank < 0 ||
+            h.start_rank > capacity)
+            return bad(fail(TSF_E_CAPACITY, "walk %d: ranks %d/%d/%d or r_cap %d outside the "
+                            "capacity %d", (int)w, h.rank, h.best_rank, h.start_rank, h.r_cap,
+                            (int)capacity));
+        const uint64_t *bufs[3] = {cur, best, start};
+        const int ranks[3] = {h.rank, h.best_rank, h.start_rank};
+        for (int q = 0; q < 3; ++q) {
+            d.rank = ranks[q];
+            tsf_scheme sc{d, U.data(), V.data(), W.data()};
+            // tsf_unpack checks the coding (TSF_E_NOT_TERNARY)
+            if ((st = tsf_unpack(bufs[q] + (size_t)w * capacity * 6, &d, &sc)))
+                return bad(fail(st, "walk %d: the %s scheme is malformed", (int)w,
+                                q == 0 ? "current" : q == 1 ? "best" : "start"));
+            if (!check_brent) continue;
+            int64_t nv = 0;
+            if ((st = tsf_verify(&sc, &nv))) return bad(st);
+            if (nv)
+                return bad(fail(TSF_E_INVALID_SCHEME, "walk %d: the %s scheme fails %lld Brent "
+                                "equations", (int)w, q == 0 ? "current" : q == 1 ? "best" : "start",
+                                (long long)nv));
+        }
+    }
+    return TSF_OK;
+}
+
 extern "C" tsf_status tsf_walk_check(const tsf_walk_params *prm, const tsf_walk_header *hdr,
                                      int32_t n_walks, int32_t *n_mismatched)
 {

@@ -22,6 +22,8 @@ EQ_ACCEPT = 42949673            # round(0.01 * 2^32): Algorithm 1's 1% equal-ran
 STATUS = {0: "TSF_OK", -1: "TSF_E_ARG", -2: "TSF_E_FORMAT", -3: "TSF_E_CAPACITY",
           -4: "TSF_E_NOT_TERNARY", -5: "TSF_E_INVALID_SCHEME", -6: "TSF_E_DEVICE",
           -7: "TSF_E_STATE"}
+TSF_E_ARG, TSF_E_FORMAT, TSF_E_CAPACITY = -1, -2, -3
+TSF_E_NOT_TERNARY, TSF_E_INVALID_SCHEME, TSF_E_DEVICE = -4, -5, -6
 TSF_E_STATE = -7
 # invariant checks of tsf_walk_checked (bits of the error word in a header's
 # `reserved` when done = -4)
@@ -169,6 +171,8 @@ def lib():
                                   C.c_int64, P(Launch), C.c_void_p]),
             ("tsf_format_slot", [C.c_int32, C.c_int32, C.c_int32]),
             ("tsf_walk_check", [P(WalkParams), C.c_void_p, C.c_int32, P(C.c_int32)]),
+            ("tsf_state_check", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.c_int32, C.c_int32, P(C.c_int32)]),
             ("tsf_scheme_invariants", [P(CScheme), C.c_void_p, P(InvariantsC)]),
             ("tsf_meta_swap", [P(CScheme), P(CScheme)]),
             ("tsf_lift", [P(CScheme), C.c_int64, C.c_int32, P(CScheme), P(LiftResultC)]),
@@ -408,6 +412,22 @@ def walk_check(prm: WalkParams, headers: np.ndarray):
     return st
 
 
+def state_check(headers, cur, best, start, capacity, brent=True):
+    """tsf_state_check on host copies of a batch's state: returns (status,
+    first failing walk or -1)."""
+    h = np.ascontiguousarray(headers, dtype=HEADER_DTYPE)
+    bufs = [np.ascontiguousarray(x).view(np.uint64) for x in (cur, best, start)]
+    first = C.c_int32(-1)
+    st = lib().tsf_state_check(h.ctypes.data_as(C.c_void_p),
+                               *[b.ctypes.data_as(C.c_void_p) for b in bufs], int(h.size),
+                               int(capacity), 1 if brent else 0, C.byref(first))
+    return st, int(first.value)
+
+
+CHECKPOINT_MAGIC = "tsf-walk-batch"
+CHECKPOINT_VERSION = 1
+
+
 class Context:
     def __init__(self):
         self.ptr = C.c_void_p()
@@ -595,6 +615,67 @@ class WalkBatch:
         check(lib().tsf_verify_batch(C.byref(self.c()), which, C.c_void_p(out.data_ptr()),
                                      self._stream()))
         return out
+
+    # ------------------------------------------------------------ checkpoints
+    def save(self, path, prm: WalkParams = None):
+        """Write the batch's whole walk state (headers, current, best and start
+        schemes, records) to `path` (a numpy .npz archive, versioned; no
+        pickled objects).  With `prm`, its tsf_params_hash is stored too."""
+        torch = self.torch
+        torch.cuda.synchronize() if self.hdr.is_cuda else None
+        np.savez(path, magic=np.array(CHECKPOINT_MAGIC), version=np.int32(CHECKPOINT_VERSION),
+                 mode=np.int32(self.mode), capacity=np.int32(self.capacity),
+                 rec_cap=np.int32(self.rec_cap), max_len=np.int32(self.max_len),
+                 params_hash=np.uint64(params_hash(prm) if prm is not None else 0),
+                 hdr=self.headers(), cur=self.cur.cpu().numpy(), best=self.best.cpu().numpy(),
+                 start=self.start.cpu().numpy(), rec=self.rec.cpu().numpy())
+
+    @classmethod
+    def load(cls, path, prm: WalkParams = None, device="cuda", brent=None):
+        """A batch from a checkpoint written by save(), refused (TsfError) when
+        it is not one (TSF_E_STATE: magic or version), when its state is
+        damaged (tsf_state_check: TSF_E_FORMAT, TSF_E_CAPACITY,
+        TSF_E_NOT_TERNARY, TSF_E_INVALID_SCHEME), or, with `prm`, when its
+        walks were run with other walk parameters (TSF_E_STATE).  brent: check
+        the Brent equations of every scheme -- on the host (default on a CPU
+        device) or, on a GPU, with tsf_verify_batch (default there)."""
+        z = np.load(path, allow_pickle=False)
+        if "magic" not in z or str(z["magic"]) != CHECKPOINT_MAGIC:
+            raise TsfError(TSF_E_STATE, "%s is not a walk-batch checkpoint" % path)
+        if int(z["version"]) != CHECKPOINT_VERSION:
+            raise TsfError(TSF_E_STATE, "checkpoint version %d, expected %d"
+                           % (int(z["version"]), CHECKPOINT_VERSION))
+        hdr = np.ascontiguousarray(z["hdr"]).view(HEADER_DTYPE)
+        cap = int(z["capacity"])
+        cur, best, start = (np.ascontiguousarray(z[k]) for k in ("cur", "best", "start"))
+        n = int(hdr.size)
+        if any(x.shape != (n, cap, 6) for x in (cur, best, start)):
+            raise TsfError(TSF_E_STATE, "checkpoint arrays do not match %d walks x %d terms"
+                           % (n, cap))
+        on_gpu = str(device).startswith("cuda")
+        host_brent = (not on_gpu) if brent is None else (brent and not on_gpu)
+        st, first = state_check(hdr, cur, best, start, cap, brent=host_brent)
+        if st:
+            raise TsfError(st, "walk %d of %s: %s" % (first, path,
+                                                      lib().tsf_last_error().decode()))
+        if prm is not None:
+            check(walk_check(prm, hdr))
+        b = cls.empty(n, cap, int(z["mode"]), int(z["max_len"]), rec_cap=int(z["rec_cap"]),
+                      device=device)
+        torch = b.torch
+        b.hdr.copy_(torch.from_numpy(hdr.view(np.uint8).reshape(-1).copy()))
+        for name, arr in (("cur", cur), ("best", best), ("start", start)):
+            getattr(b, name).copy_(torch.from_numpy(arr.view(np.int64)))
+        b.rec.copy_(torch.from_numpy(np.ascontiguousarray(z["rec"])))
+        if on_gpu and (brent is None or brent):
+            live = torch.from_numpy(hdr["done"] >= 0).to(b.hdr.device)
+            for which, label in ((0, "current"), (1, "best"), (2, "start")):
+                bad = (b.verify_device(which) != 0) & live
+                if bool(bad.any()):
+                    w = int(torch.nonzero(bad)[0].item())
+                    raise TsfError(TSF_E_INVALID_SCHEME, "walk %d of %s: the %s scheme fails "
+                                   "the Brent equations" % (w, path, label))
+        return b
 
     # ------------------------------------------------------------ read back
     def headers(self):
