@@ -794,14 +794,13 @@ struct Walker {
             sg[q] = (k < r && k != i) ? rel(xi, xk, X) : 0;
             any |= sg[q] != 0;
         }
+        // m0/m1 are read by the caller only when n0 + n1 > 0
         n0 = n1 = 0;
-#pragma unroll
-        for (int q = 0; q < S; ++q) m0[q] = m1[q] = 0;
         if (!gballot(any)) return;
         const TV<T> Ai = ld(i, A), Bi = ld(i, B);
+        uint32_t c0 = 0, c1 = 0;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            bool v0 = false, v1 = false;
             if (sg[q] != 0) {
                 const int k = q * G + gl;
                 const TV<T> Ak = ld(k, A), Bk = ld(k, B);
@@ -809,11 +808,15 @@ struct Walker {
                 const bool a1 = axpy(sg[q], Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
                 const bool a2 = axpy(sg[q], Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
                 const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
-                v0 = a1 && b1 && keep;
-                v1 = a2 && b2 && keep;
+                c0 |= (a1 && b1 && keep) ? 1u << q : 0u;
+                c1 |= (a2 && b2 && keep) ? 1u << q : 0u;
             }
-            m0[q] = gballot(v0);
-            m1[q] = gballot(v1);
+        }
+        if (!gballot((c0 | c1) != 0)) return;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            m0[q] = gballot((c0 >> q) & 1u);
+            m1[q] = gballot((c1 >> q) & 1u);
             n0 += popc64(m0[q]);
             n1 += popc64(m1[q]);
         }
@@ -835,24 +838,29 @@ struct Walker {
             sg[q] = (k < r && k != i) ? rel(xi, F[q][X], X) : 0;
             any |= sg[q] != 0;
         }
+        // m0/m1 are read by the caller only when n0 + n1 > 0
         n0 = n1 = 0;
-#pragma unroll
-        for (int q = 0; q < S; ++q) m0[q] = m1[q] = 0;
         if (!gballot(any)) return;
+        // the validity of the two roles per slot, as bits of this lane; the
+        // group's sets are built only for an attempt with a valid partner
+        uint32_t c0 = 0, c1 = 0;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            bool v0 = false, v1 = false;
             if (sg[q] != 0) {
                 const TV<T> Ak = F[q][A], Bk = F[q][B];
                 TV<T> o1, o2;
                 const bool a1 = axpy(sg[q], Ai, Ak, o1), b1 = axpy(-1, Bk, Bi, o2);
                 const bool a2 = axpy(sg[q], Bi, Bk, o1), b2 = axpy(-1, Ak, Ai, o2);
                 const bool keep = !additions || (Ai.d != Ak.d && Bi.d != Bk.d);
-                v0 = a1 && b1 && keep;
-                v1 = a2 && b2 && keep;
+                c0 |= (a1 && b1 && keep) ? 1u << q : 0u;
+                c1 |= (a2 && b2 && keep) ? 1u << q : 0u;
             }
-            m0[q] = gballot(v0);
-            m1[q] = gballot(v1);
+        }
+        if (!gballot((c0 | c1) != 0)) return;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            m0[q] = gballot((c0 >> q) & 1u);
+            m1[q] = gballot((c1 >> q) & 1u);
             n0 += popc64(m0[q]);
             n1 += popc64(m1[q]);
         }
@@ -1236,13 +1244,13 @@ struct Walker {
                 okb[u] = live && ib >= 0 && kk != ib && shares_two(tb, tk[u]);
                 any |= oka[u] || okb[u];
             }
-            if (__ballot(any)) {
+            // usually no term of these slots shares two factors with either
+            if (!__ballot(any)) continue;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    TV<T> o;
-                    oka[u] = oka[u] && merge_kind(ta, tk[u], o) >= 0;
-                    okb[u] = okb[u] && merge_kind(tb, tk[u], o) >= 0;
-                }
+            for (int u = 0; u < U; ++u) {
+                TV<T> o;
+                oka[u] = oka[u] && merge_kind(ta, tk[u], o) >= 0;
+                okb[u] = okb[u] && merge_kind(tb, tk[u], o) >= 0;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
