@@ -739,13 +739,14 @@ struct Walker {
     }
 
     // ------------------------------------------------------------------ TP
-    // With four or more slots per lane the three factors of this lane's S
+    // With four to seven slots per lane the three factors of this lane's S
     // terms (k = q*G + lane, indexes clamped to the rows) are read in one
     // round: the attempts and the cyclic search of an iteration compare
     // against these registers, since no term changes before a flip is
     // chosen.  With fewer slots each attempt reads the factors it compares
-    // (measured faster there).
-    static constexpr bool kRegSlots = !AP && S >= 4;
+    // (measured faster there); eight slots of copies would not fit in 256
+    // VGPRs.
+    static constexpr bool kRegSlots = !AP && S >= 4 && S <= 7;
     __device__ __forceinline__ void load_slots(TV<T> (&F)[S][3]) const
     {
         if constexpr (!kRegSlots) return;
@@ -1224,7 +1225,7 @@ struct Walker {
         }
         // U slots per round, their terms read before any is compared (indexes
         // clamped to the walk's rows), so the reads of a round overlap; the
-        // term-parallel kernels with four or more slots read all at once
+        // term-parallel kernels with four to seven slots read all at once
         constexpr int U = kRegSlots ? S : 2;
         const int qend = (wave_max_r() + G - 1) / G;
 #pragma unroll 1
