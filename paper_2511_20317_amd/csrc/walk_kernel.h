@@ -296,9 +296,15 @@ struct Walker {
         else
             return (m >> gshift) & ((1ull << G) - 1);
     }
+    // `lane` is the same in every lane of the group; the term-parallel kernels
+    // with register slot copies (one group per wavefront) read it with a
+    // scalar readlane instead of a lane permute
     __device__ __forceinline__ uint32_t from_lane(uint32_t v, int lane) const
     {
-        return (uint32_t)__shfl((int)v, gshift + lane);
+        if constexpr (G == 64 && kRegSlots)
+            return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+        else
+            return (uint32_t)__shfl((int)v, gshift + lane);
     }
 
     // The Philox block (iteration t, attempt att, domain dom) of this walk.
