@@ -980,6 +980,22 @@ struct Walker {
                 v1 = a2 && b2 && keep;
             }
         };
+        if (NW == 2 && !__ballot(r > 64)) {
+            // two-word sets, but no walk of the wavefront has more than 64
+            // terms: one word holds every match
+            uint64_t mm = match.w[0], s0 = 0, s1 = 0;
+            do {
+                const int kk = __builtin_ctzll(mm);
+                mm &= mm - 1;
+                bool v0, v1;
+                roles(kk, v0, v1);
+                s0 |= (v0 ? 1ull : 0ull) << kk;
+                s1 |= (v1 ? 1ull : 0ull) << kk;
+            } while (mm);
+            m0.w[0] = s0;
+            m1.w[0] = s1;
+            return;
+        }
         if (NW == 1 && !__ballot(r > 32)) {
             // every walk of the wavefront has at most 32 terms: the sets fit
             // in 32-bit words
