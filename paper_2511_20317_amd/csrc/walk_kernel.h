@@ -1897,10 +1897,13 @@ __device__ __forceinline__ void walk_body(const KArgs &a)
 // are held to 128 VGPRs, four wavefronts per SIMD, which their LDS also
 // allows at (3,3,3) (10,176 bytes per 8-walk wavefront, sixteen per CU); the
 // other indexed kernels with 32-bit masks to 168 VGPRs (three per SIMD, as
-// many as their LDS allows); the rest are not constrained.
+// many as their LDS allows); the term-parallel kernels with 64 lanes and four
+// slots per walk (capacities 193-256, e.g. (4,5,12)) also to 168 VGPRs, three
+// per SIMD, which their LDS allows; the rest are not constrained.
 template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK = false>
 __global__ void __launch_bounds__(256) __attribute__((
-    amdgpu_waves_per_eu(PK && G >= 8 ? 4 : (IX && G >= 8 && sizeof(T) == 4) ? 3 : 1))) walk_kernel(KArgs a)
+    amdgpu_waves_per_eu(PK && G >= 8 ? 4 : (IX && G >= 8 && sizeof(T) == 4) ? 3 :
+                        (!AP && G == 64 && S == 4) ? 3 : 1))) walk_kernel(KArgs a)
 {
     walk_body<G, S, T, Z2, AP, IX, PK, false>(a);
 }
