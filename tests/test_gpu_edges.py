@@ -80,3 +80,34 @@ def test_calls_that_do_nothing(ctx):
     b.walk(ctx, prm, 10)
     _sync()
     assert (b.headers()["t"] == 1000).all()
+
+
+def test_a_batch_per_format_equals_one_batch_of_all(ctx):
+    """Walks split into a batch per format (walk ids continued with
+    first_walk_id, each batch sized for its own ranks) end bit-identical to
+    the same walks in one batch of all formats (the large-format workload
+    runs this way)."""
+    import torch
+    fmts = [((4, 5, 12), 248), ((5, 6, 10), 308)]
+    per = 48
+    prm = tsf.walk_params(base_seed=4, max_iters=10 ** 6, plateau=300, t_expand=1 << 28)
+    one = tsf.WalkBatch([(tsf.init_scheme(*f), per, cap, 0) for f, cap in fmts], capacity=308,
+                        rec_cap=8)
+    one.init(ctx)
+    one.walk(ctx, prm, 400, 64, 1, 2)
+    _sync()
+    h1 = one.headers()
+    for q, (f, cap) in enumerate(fmts):
+        p = tsf.walk_params(base_seed=4, first_walk_id=q * per, max_iters=10 ** 6, plateau=300,
+                            t_expand=1 << 28)
+        b = tsf.WalkBatch([(tsf.init_scheme(*f), per, cap, 0)], capacity=cap, rec_cap=8)
+        b.init(ctx)
+        b.walk(ctx, p, 400, 64, 1, 2)
+        _sync()
+        h = b.headers()
+        sl = slice(q * per, (q + 1) * per)
+        for k in ("rank", "best_rank", "t", "plateau_start", "n_rec", "best_nnz", "counters"):
+            assert np.array_equal(h[k], h1[k][sl]), (f, k)
+        assert torch.equal(b.cur[:, :cap], one.cur[sl, :cap]) and torch.equal(b.best[:, :cap],
+                                                                             one.best[sl, :cap])
+        assert torch.equal(b.rec, one.rec[sl])
