@@ -1760,6 +1760,23 @@ __device__ __forceinline__ int flen(int m, int n, int p, int X)
 // tsf_walk_checked (after the scheme is loaded and after every iteration; a
 // walk that fails one stops with done = -4 and the error word
 // (iteration << 8) | failed checks in the header's `reserved`).
+// Issue priority of a wavefront by its progress through the call: the fewer
+// of the call's iterations it has done, the higher its priority (s_setprio;
+// between equal priorities a SIMD issues the oldest wavefront first).  The
+// wavefronts that share a SIMD would otherwise finish at staggered times, and
+// the last of them would run on a SIMD that is partly empty; with it they end
+// close together, and the next wavefronts take over whole SIMDs.  Band edges
+// at 3/8, 5/8 and 13/16 of the call.  Only the order in which the SIMD issues
+// instructions changes, never a result.
+__device__ __forceinline__ void progress_priority(int64_t it, int64_t n)
+{
+    const uint64_t q = (uint64_t)it * 64u / (uint64_t)n;  // progress in 64ths
+    if (q < 24) __builtin_amdgcn_s_setprio(3);
+    else if (q < 40) __builtin_amdgcn_s_setprio(2);
+    else if (q < 52) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 template <int G, int S, typename T, bool Z2, bool AP, bool IX, bool PK, bool CHK>
 __device__ __forceinline__ void walk_body(const KArgs &a)
 {
@@ -1861,6 +1878,7 @@ __device__ __forceinline__ void walk_body(const KArgs &a)
         for (int64_t it = 0; it < a.n_iters; ++it) {
             if (wk.reached()) done = 1;
             if (done || wk.t >= a.max_iters) break;
+            if ((it & 63) == 0) progress_priority(it, a.n_iters);
             wk.t += 1;
             wk.iteration();
             if constexpr (CHK) {
